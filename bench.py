@@ -1,0 +1,160 @@
+"""Benchmark: one block-filtered EXC evaluation (rho + E_xc + Vxc) per step on one MI355X.
+
+Workload: the 200-atom chain (2000 cartesian AOs, 75 x 302 points per atom = 4.53M points,
+128-point blocks, PBE, t_b = t_d = 1e-10), synthetic and seeded.  A step is one kldi_eval on a
+ready plan with D already in HBM: D preparation, basis on retained tiles, X = D Phi block GEMMs
+with the density epilogue, the functional, Z, the M = Phi Z^T block GEMMs, the FP64 reduction and
+the symmetrised Vxc.  The mixed path (FP32 MFMA, FP64 accumulation) is the headline; the FP64
+path is timed beside it on the same inputs.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms per EXC eval (rho+E_xc+Vxc) & TFLOP/s, mixed vs FP64, at 1e-6 Eh error"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X dense MFMA peaks
+GOLDEN = os.path.join(ROOT, "tests", "golden", "cfg1_oracle.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_path(plan, D, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.eval(D)
+    torch.cuda.synchronize()
+    st = plan.check()
+    plan.timing(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    outs = None
+    for _ in range(steps):
+        outs = plan.eval(D)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    stage, n = plan.stage_ms()
+    plan.timing(False)
+    rho, exc, vxc = outs
+    return ms, stage, st, float(exc.item()), vxc.cpu().numpy(), rho
+
+
+def cpu_baseline(p, n_sample=60000, seed=0):
+    """The FP64 oracle (dense, NumPy + host BLAS) on a random sample of grid points, scaled to one
+    full evaluation (its cost is linear in the number of points)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(p.n_points, size=min(n_sample, p.n_points), replace=False))
+    t0 = time.perf_counter()
+    oracle.eval_exc(p.atom_xyz, p.basis, p.grid.xyz[idx], p.grid.weight[idx], p.D, p.xc)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {"value": dt * 1e3 * p.n_points / len(idx), "unit": "ms/eval", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d grid points (seeded random subset), dense FP64 oracle, %.1f s measured, "
+                      "scaled linearly to all points" % (len(idx), p.n_points, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2605_10363_amd.plan import Plan
+
+    t0 = time.time()
+    p = synth.make_problem(args.config)
+    log("inputs: %s n_atoms=%d n_ao=%d n_points=%d (%.1f s)" % (p.name, p.n_atoms, p.n_ao, p.n_points,
+                                                                time.time() - t0))
+    D = torch.from_numpy(p.D).cuda()
+    res = {}
+    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
+        t0 = time.time()
+        plan = Plan.from_problem(p, prec=prec)
+        info = plan.info()
+        log("%s plan: %.0f ms, retained fraction %.4f, n_ret %d, max tiles/block %d, %d V items, %.1f GB" % (
+            prec, info["plan_ms"], info["retained_fraction"], info["n_retained_tiles"], info["max_tiles_per_block"],
+            info["n_v_items"], info["workspace_bytes"] / 1e9))
+        ms, stage, st, E, V, rho = time_path(plan, D, args.steps, args.warmup, torch)
+        log("%s: %.3f ms/eval, stages %s, pairs x %d v %d, E %.12f" % (
+            prec, ms, {k: round(v, 3) for k, v in stage.items()}, st["n_pairs_x"], st["n_pairs_v"], E))
+        res[prec] = dict(ms=ms, stage=stage, stats=st, E=E, V=V, info=info,
+                         elec=float(torch.dot(rho, torch.from_numpy(p.grid.weight).cuda()).item()))
+        plan.close()
+        del rho
+        torch.cuda.empty_cache()
+
+    mix = res["fp32"]
+    flops = mix["stats"]["gemm_flops"]
+    out = {
+        "metric": METRIC, "value": round(mix["ms"], 4), "unit": "ms/eval", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(mix["ms"], 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "200-atom chain, 2000 cartesian AOs (3s2p1d/2s1p), 4.53M points (75x302 per atom), "
+                               "128-point blocks, 32-AO tiles, PBE, t_b=t_d=1e-10",
+                   "path": "mixed: FP32 MFMA block GEMMs, FP64 functional and accumulation",
+                   "seeds": p.meta.get("seeds")},
+        "tflops": round(flops / (mix["ms"] * 1e-3) / 1e12, 3),
+        "gemm_flops_per_eval": flops,
+        "retained_fraction": mix["info"]["retained_fraction"],
+        "stage_ms": {k: round(v, 4) for k, v in mix["stage"].items()},
+        "electrons": mix["elec"], "n_occ": p.n_occ,
+    }
+    if "fp64" in res:
+        f64 = res["fp64"]
+        out["fp64"] = {"ms": round(f64["ms"], 4), "tflops": round(f64["stats"]["gemm_flops"] / (f64["ms"] * 1e-3) / 1e12, 3),
+                       "stage_ms": {k: round(v, 4) for k, v in f64["stage"].items()}}
+        out["speedup_mixed_vs_fp64"] = round(f64["ms"] / mix["ms"], 3)
+        out["err_mixed_vs_fp64"] = {"E_xc": abs(mix["E"] - f64["E"]), "V_maxabs": float(np.abs(mix["V"] - f64["V"]).max())}
+    if os.path.exists(GOLDEN):
+        g = json.load(open(GOLDEN))
+        out["err_vs_oracle"] = {"E_xc_mixed": abs(mix["E"] - g["E"])}
+        if "fp64" in res:
+            out["err_vs_oracle"]["E_xc_fp64"] = abs(res["fp64"]["E"] - g["E"])
+
+    # roofline of the dominant kernel (the larger of the two block-GEMM stages), timed live above
+    dom = "xtask" if mix["stage"]["xtask"] >= mix["stage"]["vgemm"] else "vgemm"
+    pairs = mix["stats"]["n_pairs_x"] if dom == "xtask" else mix["stats"]["n_pairs_v"]
+    kflops = 2.0 * 32 * 32 * 128 * pairs
+    achieved = kflops / (mix["stage"][dom] * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        t = json.load(open(TRAFFIC))
+        src = open(os.path.join(ROOT, "paper_2605_10363_amd", "csrc", "kernels.hip"), "rb").read()
+        if t.get("kernels_sha1") == hashlib.sha1(src).hexdigest() and dom in t.get("bytes_per_launch", {}):
+            traffic = t["bytes_per_launch"][dom]
+    out["roofline"] = {"bound": "mfma", "kernel": "k_" + dom, "achieved": round(achieved, 3),
+                       "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4),
+                       "traffic": traffic}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

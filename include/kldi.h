@@ -1,0 +1,209 @@
+/*
+ * kldi.h -- C ABI of libkldi: block-filtered exchange-correlation (EXC) integration on AMD MI355X
+ * (gfx950).
+ *
+ * The library evaluates, for a Kohn-Sham density matrix D in a contracted cartesian Gaussian basis
+ * on an atom-centred quadrature grid {(r_i, w_i)}:
+ *     Phi_{mu i} = chi_mu(r_i)                                    (paper Sec. II-A, eq. phi_def)
+ *     X = D Phi,  rho_i = sum_mu Phi_{mu i} X_{mu i}              (eq. r_equals_dphi; Appendix A,
+ *                                                                  "The density matrix")
+ *     grad rho_i = 2 sum_mu grad Phi_{mu i} X_{mu i},  sigma_i = |grad rho_i|^2      (GGA)
+ *     E_xc = sum_i w_i f(rho_i, sigma_i)                          (Appendix A, "Numerical
+ *                                                                  integration grids")
+ *     Z_{mu i} = w_i (v_rho,i Phi_{mu i} / 2 + 2 v_sigma,i grad rho_i . grad Phi_{mu i})
+ *     Vxc = Phi Z^T + Z Phi^T                                     (eq. fxc_matrix_form with b = 1
+ *                                                                  and W = diag(w v^xc), eq. w_def;
+ *                                                                  for LDA Vxc = Phi W Phi^T)
+ * as block-structured matrix products (Sec. III): the grid and the AOs are reordered (Sec. III-B.2),
+ * cut into AO tiles x grid blocks (Sec. III-B.1), tiles whose max-abs summary is below t_b are
+ * dropped (eqs. block_summary_A .. retained_blocks_B), and inside each product only the block
+ * pairs with a_pq * b_qr >= t_d are executed (eqs. block_pair_filter .. executed_block_pairs),
+ * enumerated by prefix-sum compaction (Appendix D, Alg. parallel_where).
+ *
+ * Conventions for every call:
+ *  - Every function returns a kldi_status: KLDI_OK (0) on success, a negative code otherwise; the
+ *    matching message is available from kldi_last_error() (thread-local).  No C++ exception
+ *    crosses the ABI.
+ *  - Units: bohr for positions, bohr^-2 for exponents, hartree for energies.
+ *  - Basis and grid arguments are HOST pointers; they are read during kldi_plan_create only and
+ *    copied; the caller keeps ownership.  D, rho, E_xc and Vxc of kldi_eval are DEVICE pointers
+ *    (HIP global memory on the current device) owned by the caller.
+ *  - All public floating-point data is FP64 whatever the internal precision.  Matrices are dense,
+ *    row-major, n_ao x n_ao, in the caller's AO order; rho is in the caller's grid order.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  kldi_eval only enqueues
+ *    work; results are ready after the stream is synchronised.
+ *  - Arguments are validated before any launch.  A plan is not re-entrant: concurrent kldi_eval
+ *    calls on one plan race on its workspaces.
+ */
+#ifndef KLDI_H
+#define KLDI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KLDI_OK = 0,
+  KLDI_E_ARG = -1,          /* invalid argument (NULL pointer, bad size, bad enum, ...)          */
+  KLDI_E_OOM = -2,          /* device memory for the plan's workspaces could not be allocated    */
+  KLDI_E_HIP = -3,          /* a HIP runtime call failed                                          */
+  KLDI_E_UNSUPPORTED = -4,  /* valid request this build does not implement                       */
+  KLDI_E_STATE = -5,        /* call out of order                                                  */
+  KLDI_E_NONFINITE = -6     /* non-finite entry found in D (reported by kldi_eval_check)          */
+} kldi_status;
+
+/* Exchange-correlation functional (spin-unpolarised, total density).  The paper uses M06-2X via
+ * Libxc (Sec. IV, "Numerical settings"); this library implements the published forms below. */
+typedef enum {
+  KLDI_XC_LDA_X = 1,        /* Slater exchange f = -(3/4)(3/pi)^(1/3) rho^(4/3)                  */
+  KLDI_XC_PBE = 2,          /* PBE exchange + PW92 correlation + PBE gradient correction          */
+  KLDI_XC_PBE_X = 3         /* PBE exchange only                                                   */
+} kldi_xc;
+
+/* Working precision of the block GEMMs.  The functional, rho accumulation across tiles, E_xc and
+ * the Vxc accumulation across grid segments are FP64 in every mode. */
+typedef enum {
+  KLDI_PREC_FP64 = 0,       /* FP64 operands, FP64 MFMA (v_mfma_f64_16x16x4)                     */
+  KLDI_PREC_FP32 = 1        /* FP32 operands, FP32 MFMA accumulate, FP64 flush                    */
+} kldi_prec;
+
+/* Contracted cartesian Gaussian basis (Appendix A, "Gaussian basis functions"):
+ *   chi(r) = N_rel * dx^lx dy^ly dz^lz * sum_k prim_coef[k] exp(-prim_exp[k] |r - R_atom|^2),
+ * N_rel = sqrt((2l-1)!! / ((2lx-1)!! (2ly-1)!! (2lz-1)!!)), applied by the library.  prim_coef
+ * includes the normalisation of the x^l component.  AO order = shell order, components of a shell
+ * lexicographic (x, y, z; xx, xy, xz, yy, yz, zz).  l <= 2. */
+typedef struct {
+  int32_t n_atoms;
+  const double *atom_xyz;        /* [n_atoms * 3]                                                 */
+  int32_t n_shells;
+  const int32_t *shell_atom;     /* [n_shells], 0 <= atom < n_atoms                               */
+  const int32_t *shell_l;        /* [n_shells], 0..2                                              */
+  const int32_t *shell_prim_ptr; /* [n_shells + 1], CSR offsets into prim_exp/prim_coef, strictly
+                                    increasing, first entry 0                                     */
+  const double *prim_exp;        /* [shell_prim_ptr[n_shells]], > 0                              */
+  const double *prim_coef;       /* [shell_prim_ptr[n_shells]]                                    */
+} kldi_basis;
+
+/* Quadrature grid (Sec. II-A: {(r_i, w_i)}).  point_atom is the atom whose atom-centred grid
+ * generated the point; it is the "associated atom" of the Morton grouping (Sec. III-B.2). */
+typedef struct {
+  int64_t n_points;              /* >= 1                                                          */
+  const double *xyz;             /* [n_points * 3]                                                */
+  const double *weight;          /* [n_points]                                                    */
+  const int32_t *point_atom;     /* [n_points], 0 <= atom < n_atoms                               */
+} kldi_grid;
+
+typedef struct {
+  double t_b;                    /* block-retention threshold (eq. block_filter_A), >= 0          */
+  double t_d;                    /* block-pair execution threshold (eq. block_pair_filter), >= 0  */
+  double rho_cut;                /* points with rho <= rho_cut get f = v = 0, >= 0                 */
+  int32_t grid_block;            /* G, points per grid block; this build supports 128             */
+  int32_t ao_block;              /* d, AOs per tile; this build supports 32                       */
+  int32_t prec;                  /* kldi_prec                                                     */
+  int32_t xc;                    /* kldi_xc                                                       */
+  int32_t v_segment;             /* grid blocks per Vxc accumulation segment; 0 = chosen by plan  */
+  int32_t reserved;
+} kldi_opts;
+
+typedef struct kldi_plan kldi_plan;
+
+typedef struct {
+  int32_t n_ao, n_tiles;               /* AOs and AO tiles (d AOs each, last one padded)          */
+  int64_t n_points, n_blocks;          /* grid points and grid blocks (G each, last one padded)   */
+  int64_t n_candidate_tiles;           /* (tile, block) pairs passing the shell-radius pre-filter */
+  int64_t n_retained_tiles;            /* |S_Phi|: (tile, block) pairs with max-abs >= t_b        */
+  double retained_fraction;            /* n_retained_tiles / (n_tiles * n_blocks)                 */
+  int32_t max_tiles_per_block;         /* max over blocks of |S_r|                                */
+  int32_t v_segment;                   /* grid blocks per Vxc segment                             */
+  int64_t n_v_items;                   /* Vxc work items (chunk pair x segment)                  */
+  int64_t workspace_bytes;             /* device bytes held by the plan                           */
+  double plan_ms;                      /* wall time of kldi_plan_create                           */
+} kldi_plan_info_t;
+
+typedef struct {
+  int64_t n_pairs_x;                   /* executed (p, q, r) tile triples of X = D Phi            */
+  int64_t n_pairs_v;                   /* executed (p, q, r) tile triples of M = Phi Z^T          */
+  double gemm_flops;                   /* 2 d^2 G (n_pairs_x + n_pairs_v): algorithmic GEMM work  */
+  int32_t nonfinite_d;                 /* 1 if D held a NaN or Inf                                */
+} kldi_eval_stats_t;
+
+/* Stages of one evaluation, for kldi_eval_timing. */
+typedef enum {
+  KLDI_STAGE_DPREP = 0,     /* D to internal tiles + block summaries a_pq                          */
+  KLDI_STAGE_BASIS = 1,     /* Phi on retained tiles                                               */
+  KLDI_STAGE_XTASK = 2,     /* X = D Phi block GEMMs, rho / grad rho, functional, Z                */
+  KLDI_STAGE_VGEMM = 3,     /* M = Phi Z^T block GEMMs over grid segments                         */
+  KLDI_STAGE_VFINAL = 4,    /* FP64 segment reduction, symmetrise, un-permute, E_xc sum           */
+  KLDI_N_STAGES = 5
+} kldi_stage;
+
+/* Fills *opts with defaults: t_b = t_d = 1e-10, rho_cut = 1e-14, G = 128, d = 32, FP64, LDA. */
+void kldi_opts_default(kldi_opts *opts);
+
+/* Builds the geometry-level structure reused across evaluations (Sec. III-B.3: reordering and
+ * filtering once per geometry): Morton grid order and atom-grouped AO order (Sec. III-B.2,
+ * eq. morton_code), grid blocks and AO tiles, shell cut-off radii, the exact block maxima of Phi
+ * (and grad Phi for GGA) on the device, the retained set S_Phi with its block-compressed column
+ * lists BCS(C) (Appendix C), the Vxc work list, and all device workspaces.
+ * basis, grid, opts: host pointers (copied).  stream: hipStream_t or NULL.  *out receives the
+ * plan, owned by the caller and released with kldi_plan_destroy.
+ * Errors: KLDI_E_ARG (validation), KLDI_E_UNSUPPORTED (grid_block != 128, ao_block != 32),
+ * KLDI_E_OOM, KLDI_E_HIP.  On error *out is set to NULL and nothing is leaked. */
+kldi_status kldi_plan_create(const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts,
+                             void *stream, kldi_plan **out);
+
+/* Releases the plan and its device memory (synchronises its device).  NULL is a no-op. */
+kldi_status kldi_plan_destroy(kldi_plan *plan);
+
+/* Copies the plan's sizes and structure statistics to *out (host). */
+kldi_status kldi_plan_info(const kldi_plan *plan, kldi_plan_info_t *out);
+
+/* Copies the plan's structure to caller-allocated HOST arrays (any may be NULL):
+ *   ao_perm[n_ao]             internal AO index -> caller AO index
+ *   pt_perm[n_points]         internal point index -> caller point index
+ *   retained[n_tiles*n_blocks] 1 if (tile p, block r) is in S_Phi, at [r * n_tiles + p]
+ *   phi_max[n_tiles*n_blocks]  max |Phi| of tile (p, r) if retained, else 0, at [r * n_tiles + p]
+ * For tests and diagnostics (Sec. III-B.2 orders, eq. retained_blocks_B). */
+kldi_status kldi_plan_structure(const kldi_plan *plan, int32_t *ao_perm, int64_t *pt_perm,
+                                uint8_t *retained, double *phi_max);
+
+/* One EXC evaluation on a ready plan (Sec. III-C): per-evaluation pair screening and
+ * compaction, basis evaluation on retained tiles, X = D Phi block GEMMs with the rho / grad rho
+ * epilogue, the functional, Z, the M = Phi Z^T block GEMMs, the FP64 reduction over grid
+ * segments, symmetrisation and un-permutation.
+ *   D_dev   [n_ao*n_ao] FP64, device, symmetric, caller AO order (read during the call only)
+ *   rho_dev [n_points]  FP64, device, caller grid order, or NULL
+ *   exc_dev [1]         FP64, device: E_xc
+ *   vxc_dev [n_ao*n_ao] FP64, device, symmetric, caller AO order, or NULL (then the M products are
+ *                       skipped)
+ * Only enqueues work on `stream`.  Errors: KLDI_E_ARG (NULL plan/D/exc), KLDI_E_HIP. */
+kldi_status kldi_eval(kldi_plan *plan, const double *D_dev, double *rho_dev, double *exc_dev,
+                      double *vxc_dev, void *stream);
+
+/* Synchronises `stream` and copies the counters of the last kldi_eval on this plan to *out
+ * (host): executed block-pair counts (the n_P of Sec. III-D), the algorithmic GEMM FLOPs they
+ * imply, and whether D held a non-finite value (then returns KLDI_E_NONFINITE). */
+kldi_status kldi_eval_check(kldi_plan *plan, kldi_eval_stats_t *out, void *stream);
+
+/* Turns per-stage timing on (enable != 0) or off and clears the accumulated samples.  While on,
+ * each kldi_eval records HIP events between its stages on its stream (up to 256 evaluations are
+ * kept; older ones are overwritten). */
+kldi_status kldi_plan_timing(kldi_plan *plan, int32_t enable);
+
+/* Synchronises the recorded events and writes the mean duration in ms of each stage over the
+ * evaluations timed since kldi_plan_timing(plan, 1) to stage_ms[KLDI_N_STAGES] (host), and their
+ * number to *n_evals (host, may be NULL).  Stages that did not run (no Vxc requested) read 0. */
+kldi_status kldi_eval_timing(kldi_plan *plan, double *stage_ms, int32_t *n_evals);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *kldi_last_error(void);
+
+/* ABI version, currently 1. */
+int32_t kldi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KLDI_H */

@@ -1,0 +1,149 @@
+"""GPU parity: libkldi (through its C ABI) against the FP64 CPU oracle on the same seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import reorder
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def Plan():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_10363_amd.plan import Plan
+    return Plan
+
+
+def run(Plan, p, xc, prec="fp64", t_b=1e-10, t_d=1e-10, **kw):
+    print("case: %s xc=%s prec=%s t_b=%g t_d=%g n_ao=%d n_points=%d" % (p.name, xc, prec, t_b, t_d, p.n_ao,
+                                                                         p.n_points), flush=True)
+    plan = Plan.from_problem(p, xc=xc, prec=prec, t_b=t_b, t_d=t_d, **kw)
+    D = torch.from_numpy(p.D).cuda()
+    rho, exc, vxc = plan.eval(D)
+    st = plan.check()
+    out = dict(rho=rho.cpu().numpy(), E=float(exc.item()), V=vxc.cpu().numpy(), stats=st, info=plan.info(),
+               plan=plan)
+    return out
+
+
+def blocked_ref(p, xc, t_b=1e-10, t_d=1e-10):
+    return oracle.eval_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc,
+                               t_b=t_b, t_d=t_d, d_ao=32, G=128)
+
+
+TINY = [
+    # (n_atoms, n_rad, n_ang, n_occ, seed): ragged AO counts and grid lengths
+    (2, 10, 26, 2, 41),
+    (4, 16, 50, 4, 42),
+    (5, 13, 38, 5, 43),
+]
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe", "pbe_x"])
+@pytest.mark.parametrize("shape", TINY)
+def test_tiny_fp64_matches_blocked_oracle(Plan, xc, shape):
+    n_atoms, n_rad, n_ang, n_occ, seed = shape
+    p = synth.tiny_problem(n_atoms=n_atoms, n_rad=n_rad, n_ang=n_ang, n_occ=n_occ, xc=xc, seed=seed, box_A=4.0)
+    ref = blocked_ref(p, xc)
+    g = run(Plan, p, xc)
+    assert abs(g["E"] - ref["E"]) <= 1e-12 * max(1.0, abs(ref["E"]))
+    assert np.abs(g["V"] - ref["V"]).max() <= 1e-12 * max(1.0, np.abs(ref["V"]).max())
+    assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * max(1.0, np.abs(ref["rho"]).max())
+    assert np.array_equal(g["V"], g["V"].T)
+    assert g["stats"]["n_pairs_x"] == ref["nP_X"]
+    assert g["stats"]["n_pairs_v"] == ref["nP_M"]
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_tiny_unscreened_matches_dense_oracle(Plan, xc):
+    p = synth.tiny_problem(n_atoms=4, n_rad=14, n_ang=26, n_occ=4, xc=xc, seed=44, box_A=5.0)
+    ref = oracle.eval_exc(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.D, xc)
+    g = run(Plan, p, xc, t_b=0.0, t_d=0.0)
+    assert g["info"]["retained_fraction"] == 1.0
+    assert abs(g["E"] - ref["E"]) <= 1e-12 * abs(ref["E"])
+    assert np.abs(g["V"] - ref["V"]).max() <= 1e-12 * np.abs(ref["V"]).max()
+    assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * np.abs(ref["rho"]).max()
+
+
+def test_plan_structure_matches_oracle_orders_and_retention(Plan, cfg0):
+    p = cfg0
+    ref = blocked_ref(p, "lda")
+    plan = Plan.from_problem(p, xc="lda")
+    ao, pt, ret, bmax = plan.structure()
+    assert np.array_equal(ao, ref["ao_perm"])
+    assert np.array_equal(pt, ref["pt_perm"])
+    s = ref["s"].T          # oracle [tile, block] -> [block, tile]
+    sure = np.abs(s - 1e-10) > 1e-6 * 1e-10
+    assert np.array_equal(ret.astype(bool)[sure], ref["S_phi"].T[sure])
+    m = ret.astype(bool)
+    assert np.allclose(bmax[m], ref["b"].T[m], rtol=1e-13, atol=0)
+    plan.close()
+
+
+def test_cfg0_fp64_and_fp32(Plan, cfg0):
+    p = cfg0
+    ref = blocked_ref(p, "lda")
+    dense = oracle.eval_exc(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.D, "lda")
+    g = run(Plan, p, "lda", "fp64")
+    assert abs(g["E"] - ref["E"]) <= 1e-12 * abs(ref["E"])
+    assert np.abs(g["V"] - ref["V"]).max() <= 1e-12 * np.abs(ref["V"]).max()
+    assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * np.abs(ref["rho"]).max()
+    assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
+    # spec accuracy of the FP32 form against the unscreened FP64 oracle
+    f = run(Plan, p, "lda", "fp32")
+    assert abs(f["E"] - dense["E"]) < 1e-6
+    assert np.abs(f["V"] - dense["V"]).max() < 1e-7
+    big = dense["rho"] > 1e-8
+    assert np.max(np.abs(f["rho"][big] - dense["rho"][big]) / dense["rho"][big]) < 1e-5
+    print("cfg0 fp32: dE %.3e dV %.3e" % (abs(f["E"] - dense["E"]), np.abs(f["V"] - dense["V"]).max()))
+
+
+def test_cfg0_geometry_pbe_fp64(Plan, cfg0):
+    p = cfg0
+    ref = blocked_ref(p, "pbe")
+    g = run(Plan, p, "pbe", "fp64")
+    assert abs(g["E"] - ref["E"]) <= 1e-12 * abs(ref["E"])
+    assert np.abs(g["V"] - ref["V"]).max() <= 1e-12 * np.abs(ref["V"]).max()
+    assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
+
+
+def test_bitwise_deterministic(Plan):
+    p = synth.tiny_problem(n_atoms=5, n_rad=14, n_ang=38, n_occ=5, xc="pbe", seed=45, box_A=5.0)
+    plan = Plan.from_problem(p, xc="pbe")
+    D = torch.from_numpy(p.D).cuda()
+    a = [t.cpu().numpy().copy() for t in plan.eval(D)]
+    b = [t.cpu().numpy().copy() for t in plan.eval(D)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    plan.close()
+
+
+def test_nonfinite_density_matrix_is_reported(Plan):
+    p = synth.tiny_problem(n_atoms=2, n_rad=10, n_ang=26, n_occ=2, seed=46)
+    plan = Plan.from_problem(p)
+    D = torch.from_numpy(p.D).cuda()
+    D[1, 2] = float("nan")
+    plan.eval(D)
+    from paper_2605_10363_amd._lib import KldiError
+    with pytest.raises(KldiError) as e:
+        plan.check()
+    assert e.value.status == -6
+    plan.close()
+
+
+def test_rho_only_and_no_vxc(Plan):
+    p = synth.tiny_problem(n_atoms=3, n_rad=12, n_ang=26, n_occ=3, xc="pbe", seed=47)
+    ref = blocked_ref(p, "pbe")
+    plan = Plan.from_problem(p, xc="pbe")
+    rho, exc, vxc = plan.eval(torch.from_numpy(p.D).cuda(), vxc=False)
+    assert vxc is None
+    assert abs(float(exc.item()) - ref["E"]) <= 1e-12 * abs(ref["E"])
+    assert np.abs(rho.cpu().numpy() - ref["rho"]).max() <= 1e-12 * np.abs(ref["rho"]).max()
+    plan.close()
