@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (HBM-counter calibration for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus)
@@ -92,6 +94,12 @@ def main():
     log("inputs: %s n_atoms=%d n_ao=%d n_points=%d (%.1f s)" % (p.name, p.n_atoms, p.n_ao, p.n_points,
                                                                 time.time() - t0))
     D = torch.from_numpy(p.D).cuda()
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     res = {}
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
         t0 = time.time()

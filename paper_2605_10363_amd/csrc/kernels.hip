@@ -348,7 +348,7 @@ struct XArgs {
 
 // One workgroup per grid block r (4 waves; wave w owns output tile 4c + w of each chunk c).
 template <class T, bool GGA>
-__global__ __launch_bounds__(NT, 2) void k_xtask(XArgs A) {
+__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1) void k_xtask(XArgs A) {
   typedef Mma<T> M;
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
@@ -361,14 +361,15 @@ __global__ __launch_bounds__(NT, 2) void k_xtask(XArgs A) {
   const T *Dt = static_cast<const T *>(A.Dt);
   const T *phi = static_cast<const T *>(A.phi);
 
-  // LDS: the K loop stages A (128 x 32) and B (32 x 128) tiles; the epilogue reuses the same bytes
-  // for two 32 x 128 X tiles at a time
-  constexpr int kStageBytes = (128 * LDA_S + 32 * LDB_S) * int(sizeof(T));
+  // LDS: the K loop double-buffers A (128 x 32) and B (32 x 128) tiles; the epilogue reuses the
+  // same bytes for two 32 x 128 X tiles at a time
+  constexpr int kA = 128 * LDA_S, kB = 32 * LDB_S;
+  constexpr int kStageBytes = 2 * (kA + kB) * int(sizeof(T));
   static_assert(kStageBytes >= 2 * kD * kG * int(sizeof(T)), "epilogue X tiles must fit the staging area");
   __shared__ __align__(16) unsigned char s_raw[kStageBytes];
-  T *sA = reinterpret_cast<T *>(s_raw);
-  T *sB = sA + 128 * LDA_S;
-  T *Xs = sA;                       // [2][32][kG] in the epilogue
+  T *sA = reinterpret_cast<T *>(s_raw);   // [2][kA]
+  T *sB = sA + 2 * kA;                     // [2][kB]
+  T *Xs = sA;                              // [2][32][kG] in the epilogue
   __shared__ int s_p[kMaxNp];
   __shared__ int s_list[kMaxNp];
   __shared__ int s_w[4];
@@ -415,48 +416,72 @@ __global__ __launch_bounds__(NT, 2) void k_xtask(XArgs A) {
     }
     __syncthreads();
 
-    // ---- X = sum over executable q of D_pq Phi_qr (MFMA, tiles staged in LDS)
+    // ---- X = sum over executable q of D_pq Phi_qr (MFMA).  Tiles of step e+1 are fetched into
+    // registers while step e multiplies out of LDS; one barrier per step (double-buffered LDS)
     acc_t acc[2][8];
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 8; ++tj) acc[ti][tj] = acc_t{};
     const bool has_w = 4 * c + w < np;
-    for (int e = 0; e < n_list; ++e) {
-      const int ent = s_list[e];
-      const int t = ent & 0xffff, mask = ent >> 16;
+    constexpr int UA = (kD * kD) / E;   // 16-byte units per D tile
+    constexpr int UB = (kD * kG) / E;   // units per Phi tile
+    constexpr int NA = 4 * UA / NT, NB = UB / NT;
+    uint4 ra[NA], rb[NB];
+    auto fetch = [&](int e) {
+      const int t = s_list[e] & 0xffff;
       const int q = s_p[t];
-      // A: four 32x32 D tiles (rows of the four output tiles), B: the 32x128 Phi tile of (q, r)
-      constexpr int UA = (kD * kD) / E;  // units per D tile
-      for (int u = tid; u < 4 * UA; u += NT) {
-        const int ww = u / UA, uu = u % UA;
-        const int e0 = uu * E, i = e0 / kD, j = e0 % kD;
-        uint4 val = make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < NA; ++m) {
+        const int u = tid + NT * m, ww = u / UA, uu = u % UA;
+        ra[m] = make_uint4(0, 0, 0, 0);
         if (4 * c + ww < np)
-          val = reinterpret_cast<const uint4 *>(Dt + (size_t(s_p[4 * c + ww]) * n_tiles + q) * (kD * kD))[uu];
-        lds_store_unit<T>(&sA[(32 * ww + i) * LDA_S + j], val);
+          ra[m] = reinterpret_cast<const uint4 *>(Dt + (size_t(s_p[4 * c + ww]) * n_tiles + q) * (kD * kD))[uu];
       }
-      constexpr int UB = (kD * kG) / E;
       const uint4 *src = reinterpret_cast<const uint4 *>(phi + size_t(k0 + t) * (kD * kG));
-      for (int u = tid; u < UB; u += NT) {
-        const int e0 = u * E, i = e0 / kG, j = e0 % kG;
-        lds_store_unit<T>(&sB[i * LDB_S + j], src[u]);
+#pragma unroll
+      for (int m = 0; m < NB; ++m) rb[m] = src[tid + NT * m];
+    };
+    auto stash = [&](int buf) {
+      T *a = sA + buf * kA;
+      T *b = sB + buf * kB;
+#pragma unroll
+      for (int m = 0; m < NA; ++m) {
+        const int u = tid + NT * m, ww = u / UA, e0 = (u % UA) * E;
+        lds_store_unit<T>(&a[(32 * ww + e0 / kD) * LDA_S + e0 % kD], ra[m]);
       }
-      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < NB; ++m) {
+        const int e0 = (tid + NT * m) * E;
+        lds_store_unit<T>(&b[(e0 / kG) * LDB_S + e0 % kG], rb[m]);
+      }
+    };
+    if (n_list > 0) {
+      fetch(0);
+      stash(0);
+    }
+    __syncthreads();
+    for (int e = 0; e < n_list; ++e) {
+      const int buf = e & 1;
+      const int mask = s_list[e] >> 16;
+      if (e + 1 < n_list) fetch(e + 1);
       if ((mask >> w) & 1) {
+        const T *a = sA + buf * kA;
+        const T *b = sB + buf * kB;
 #pragma unroll 2
         for (int kk = 0; kk < 8; ++kk) {
           const int kc = 4 * kk + (l >> 4);
-          const T a0 = sA[(32 * w + (l & 15)) * LDA_S + kc];
-          const T a1 = sA[(32 * w + 16 + (l & 15)) * LDA_S + kc];
+          const T a0 = a[(32 * w + (l & 15)) * LDA_S + kc];
+          const T a1 = a[(32 * w + 16 + (l & 15)) * LDA_S + kc];
 #pragma unroll
           for (int tj = 0; tj < 8; ++tj) {
-            const T b = sB[kc * LDB_S + 16 * tj + (l & 15)];
-            acc[0][tj] = M::mma(a0, b, acc[0][tj]);
-            acc[1][tj] = M::mma(a1, b, acc[1][tj]);
+            const T bv = b[kc * LDB_S + 16 * tj + (l & 15)];
+            acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
+            acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
           }
         }
       }
+      if (e + 1 < n_list) stash(buf ^ 1);
       __syncthreads();
     }
 
@@ -584,7 +609,7 @@ struct VArgs {
 // One workgroup per (row chunk pc, column chunk qc, segment of grid blocks).  Wave w owns AO tile
 // 4pc + w (32 rows); columns are the 128 AOs of tiles 4qc .. 4qc+3.
 template <class T>
-__global__ __launch_bounds__(NT, 2) void k_vgemm(VArgs A) {
+__global__ __launch_bounds__(NT, 1) void k_vgemm(VArgs A) {
   typedef Mma<T> M;
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
@@ -596,8 +621,9 @@ __global__ __launch_bounds__(NT, 2) void k_vgemm(VArgs A) {
   const T *phi = static_cast<const T *>(A.phi);
   const T *zws = static_cast<const T *>(A.zws);
 
-  __shared__ __align__(16) T sA[128 * LDA_S];
-  __shared__ __align__(16) T sB[128 * LDA_S];
+  constexpr int kS = 128 * LDA_S;                 // one A or B stage
+  __shared__ __align__(16) T sA[2 * kS];
+  __shared__ __align__(16) T sB[2 * kS];
   __shared__ int s_r[NT];
   __shared__ int s_m[NT];
   __shared__ int s_k[NT * 8];   // positions within S_r of the 4 row tiles and 4 column tiles
@@ -652,44 +678,70 @@ __global__ __launch_bounds__(NT, 2) void k_vgemm(VArgs A) {
       pairs += __popc(mask);
     }
     __syncthreads();
-    for (int e = 0; e < tot; ++e) {
-      const int rr = s_r[e], m = s_m[e];
-      const int64_t bo = A.st.blk_off[rr];
-      const int wm = (m >> (4 * w)) & 15;
-      for (int sub = 0; sub < 4; ++sub) {
-        // A rows: Phi tiles of 4pc..4pc+3, points 32 sub .. 32 sub + 31; B rows: Z tiles of 4qc..
-        constexpr int UR = kD / E;           // units per 32-element row slice
-        constexpr int UT = kD * UR;          // units per tile slab
-        for (int u = tid; u < 8 * UT; u += NT) {
-          const int which = u / UT, uu = u % UT;  // which: 0..3 A tiles, 4..7 B tiles
-          const int i = uu / UR, j0 = (uu % UR) * E;
-          const int kk = s_k[e * 8 + which];
-          uint4 val = make_uint4(0, 0, 0, 0);
-          if (kk >= 0) {
-            const T *src = ((which < 4) ? phi : zws) + size_t(bo + kk) * (kD * kG) + i * kG + 32 * sub + j0;
-            val = *reinterpret_cast<const uint4 *>(src);
-          }
-          T *dst = (which < 4) ? &sA[(32 * which + i) * LDA_S + j0] : &sB[(32 * (which - 4) + i) * LDA_S + j0];
-          lds_store_unit<T>(dst, val);
-        }
-        __syncthreads();
-        if (wm) {
-#pragma unroll 2
-          for (int kk = 0; kk < 8; ++kk) {
-            const int kc = 4 * kk + (l >> 4);
-            const T a0 = sA[(32 * w + (l & 15)) * LDA_S + kc];
-            const T a1 = sA[(32 * w + 16 + (l & 15)) * LDA_S + kc];
+    // stages s = 4 e + sub: entry e of the compacted list, points 32 sub .. 32 sub + 31
+    constexpr int UR = kD / E;          // units per 32-element row slice
+    constexpr int UT = kD * UR;         // units per 32 x 32 slab
+    constexpr int NU = 8 * UT / NT;     // units per thread (4 A slabs + 4 B slabs)
+    uint4 rv[NU];
+    int rmask = 0;                      // which units of this thread were fetched
+    auto fetch = [&](int st) {
+      const int e = st >> 2, sub = st & 3;
+      const int m = s_m[e];
+      const int64_t bo = A.st.blk_off[s_r[e]];
+      rmask = 0;
 #pragma unroll
-            for (int tj = 0; tj < 8; ++tj) {
-              if ((wm >> (tj >> 1)) & 1) {
-                const T b = sB[(16 * tj + (l & 15)) * LDA_S + kc];
-                acc[0][tj] = M::mma(a0, b, acc[0][tj]);
-                acc[1][tj] = M::mma(a1, b, acc[1][tj]);
-              }
+      for (int k = 0; k < NU; ++k) {
+        const int u = tid + NT * k, which = u / UT, uu = u % UT;
+        const int i = uu / UR, j0 = (uu % UR) * E;
+        // a row tile is needed if any of its pairs runs, a column tile likewise
+        const bool need = (which < 4) ? ((m >> (4 * which)) & 15) != 0 : ((m >> (which - 4)) & 0x1111) != 0;
+        const int kk = s_k[e * 8 + which];
+        if (need && kk >= 0) {
+          const T *src = ((which < 4) ? phi : zws) + size_t(bo + kk) * (kD * kG) + i * kG + 32 * sub + j0;
+          rv[k] = *reinterpret_cast<const uint4 *>(src);
+          rmask |= 1 << k;
+        }
+      }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+      for (int k = 0; k < NU; ++k) {
+        if (!((rmask >> k) & 1)) continue;
+        const int u = tid + NT * k, which = u / UT, uu = u % UT;
+        const int i = uu / UR, j0 = (uu % UR) * E;
+        T *dst = (which < 4) ? &sA[buf * kS + (32 * which + i) * LDA_S + j0]
+                             : &sB[buf * kS + (32 * (which - 4) + i) * LDA_S + j0];
+        lds_store_unit<T>(dst, rv[k]);
+      }
+    };
+    const int nst = 4 * tot;
+    if (nst > 0) {
+      fetch(0);
+      stash(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+      const int buf = st & 1;
+      const int wm = (s_m[st >> 2] >> (4 * w)) & 15;
+      if (st + 1 < nst) fetch(st + 1);
+      if (wm) {
+        const T *a = sA + buf * kS;
+        const T *b = sB + buf * kS;
+#pragma unroll 2
+        for (int kk = 0; kk < 8; ++kk) {
+          const int kc = 4 * kk + (l >> 4);
+          const T a0 = a[(32 * w + (l & 15)) * LDA_S + kc];
+          const T a1 = a[(32 * w + 16 + (l & 15)) * LDA_S + kc];
+#pragma unroll
+          for (int tj = 0; tj < 8; ++tj) {
+            if ((wm >> (tj >> 1)) & 1) {
+              const T bv = b[(16 * tj + (l & 15)) * LDA_S + kc];
+              acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
+              acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
             }
           }
         }
-        if (sizeof(T) == 4 && wm) {
+        if (sizeof(T) == 4) {
           // FP32 accumulation spans one 32-point slab; the running sum over slabs and grid blocks
           // is FP64
 #pragma unroll
@@ -701,8 +753,9 @@ __global__ __launch_bounds__(NT, 2) void k_vgemm(VArgs A) {
               acc[ti][tj] = acc_t{};
             }
         }
-        __syncthreads();
       }
+      if (st + 1 < nst) stash(buf ^ 1);
+      __syncthreads();
     }
     __syncthreads();
   }
