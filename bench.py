@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--v-segment", type=int, default=0, help="grid blocks per Vxc segment (0 = plan's choice)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM-counter calibration for profiling)")
     args = ap.parse_args()
@@ -103,7 +104,7 @@ def main():
     res = {}
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
         t0 = time.time()
-        plan = Plan.from_problem(p, prec=prec)
+        plan = Plan.from_problem(p, prec=prec, v_segment=args.v_segment)
         info = plan.info()
         log("%s plan: %.0f ms, retained fraction %.4f, n_ret %d, max tiles/block %d, %d V items, %.1f GB" % (
             prec, info["plan_ms"], info["retained_fraction"], info["n_retained_tiles"], info["max_tiles_per_block"],
@@ -146,8 +147,8 @@ def main():
             out["err_vs_oracle"]["E_xc_fp64"] = abs(res["fp64"]["E"] - g["E"])
 
     # roofline of the dominant kernel (the larger of the two block-GEMM stages), timed live above
-    dom = "xtask" if mix["stage"]["xtask"] >= mix["stage"]["vgemm"] else "vgemm"
-    pairs = mix["stats"]["n_pairs_x"] if dom == "xtask" else mix["stats"]["n_pairs_v"]
+    dom = "xgemm" if mix["stage"]["xgemm"] >= mix["stage"]["vgemm"] else "vgemm"
+    pairs = mix["stats"]["n_pairs_x"] if dom == "xgemm" else mix["stats"]["n_pairs_v"]
     kflops = 2.0 * 32 * 32 * 128 * pairs
     achieved = kflops / (mix["stage"][dom] * 1e-3) / 1e12
     traffic = None

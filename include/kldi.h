@@ -104,7 +104,8 @@ typedef struct {
   int32_t prec;                  /* kldi_prec                                                     */
   int32_t xc;                    /* kldi_xc                                                       */
   int32_t v_segment;             /* grid blocks per Vxc accumulation segment; 0 = chosen by plan  */
-  int32_t reserved;
+  int32_t chunk_tiles;           /* max retained tiles whose Phi/Z are held at once (the grid is
+                                    processed in chunks of whole Vxc segments); 0 = fit to memory */
 } kldi_opts;
 
 typedef struct kldi_plan kldi_plan;
@@ -119,6 +120,7 @@ typedef struct {
   int32_t v_segment;                   /* grid blocks per Vxc segment                             */
   int64_t n_v_items;                   /* Vxc work items (chunk pair x segment)                  */
   int64_t workspace_bytes;             /* device bytes held by the plan                           */
+  int32_t n_grid_chunks;               /* chunks of grid blocks per evaluation                    */
   double plan_ms;                      /* wall time of kldi_plan_create                           */
 } kldi_plan_info_t;
 
@@ -127,16 +129,18 @@ typedef struct {
   int64_t n_pairs_v;                   /* executed (p, q, r) tile triples of M = Phi Z^T          */
   double gemm_flops;                   /* 2 d^2 G (n_pairs_x + n_pairs_v): algorithmic GEMM work  */
   int32_t nonfinite_d;                 /* 1 if D held a NaN or Inf                                */
+  int64_t n_points_mlp;                /* grid points evaluated by an attached functional surrogate */
 } kldi_eval_stats_t;
 
 /* Stages of one evaluation, for kldi_eval_timing. */
 typedef enum {
   KLDI_STAGE_DPREP = 0,     /* D to internal tiles + block summaries a_pq                          */
   KLDI_STAGE_BASIS = 1,     /* Phi on retained tiles                                               */
-  KLDI_STAGE_XTASK = 2,     /* X = D Phi block GEMMs, rho / grad rho, functional, Z                */
-  KLDI_STAGE_VGEMM = 3,     /* M = Phi Z^T block GEMMs over grid segments                         */
-  KLDI_STAGE_VFINAL = 4,    /* FP64 segment reduction, symmetrise, un-permute, E_xc sum           */
-  KLDI_N_STAGES = 5
+  KLDI_STAGE_XGEMM = 2,     /* X = D Phi block GEMMs with the rho / grad rho epilogue              */
+  KLDI_STAGE_XFUNC = 3,     /* rho reduction, functional, E_xc partials, Z on retained tiles       */
+  KLDI_STAGE_VGEMM = 4,     /* M = Phi Z^T block GEMMs over grid segments                         */
+  KLDI_STAGE_VFINAL = 5,    /* FP64 segment reduction, symmetrise, un-permute, E_xc sum           */
+  KLDI_N_STAGES = 6
 } kldi_stage;
 
 /* Fills *opts with defaults: t_b = t_d = 1e-10, rho_cut = 1e-14, G = 128, d = 32, FP64, LDA. */
@@ -186,6 +190,72 @@ kldi_status kldi_eval(kldi_plan *plan, const double *D_dev, double *rho_dev, dou
  * (host): executed block-pair counts (the n_P of Sec. III-D), the algorithmic GEMM FLOPs they
  * imply, and whether D held a non-finite value (then returns KLDI_E_NONFINITE). */
 kldi_status kldi_eval_check(kldi_plan *plan, kldi_eval_stats_t *out, void *stream);
+
+/* rho and sigma = |grad rho|^2 on the grid for D (the density part of kldi_eval: screening, basis,
+ * X = D Phi, the rho / grad rho epilogue), in caller grid order.  rho_dev, sigma_dev: [n_points]
+ * FP64 device arrays, either may be NULL (not both).  sigma is |grad rho|^2 for GGA plans and 0 for
+ * LDA plans.  Used, e.g., to sample the (rho, sigma) points a functional surrogate is trained on. */
+kldi_status kldi_eval_grid(kldi_plan *plan, const double *D_dev, double *rho_dev, double *sigma_dev, void *stream);
+
+/* The library's exchange-correlation functional on device arrays: f (energy per volume), v_rho =
+ * df/drho and v_sigma = df/dsigma at n points, zero where rho <= rho_cut.  sigma_dev and
+ * vsigma_dev may be NULL for KLDI_XC_LDA_X.  FP64 device pointers. */
+kldi_status kldi_xc_eval(int32_t xc, const double *rho_dev, const double *sigma_dev, int64_t n, double rho_cut,
+                         double *f_dev, double *vrho_dev, double *vsigma_dev, void *stream);
+
+/* ---- functional surrogate (learned form; not in the paper) ---------------------------------------
+ * A 2-64-64-64-3 SiLU network maps x = (n(log rho), n(log sigma)) -- n(.) the affine map of the
+ * training range box onto [-1, 1], sigma floored at 1e-30 -- to three standardised heads whose
+ * de-standardised values are f / rho^(4/3), v_rho / rho^(1/3) and v_sigma * rho^(4/3).  Parameters
+ * (8707) are ordered W1[64][2], b1[64], W2[64][64], b2, W3[64][64], b3, W4[3][64], b4[3], W row-major
+ * [out][in].  Training (FP32 master weights, Adam) and inference (BF16 weights, FP32 accumulation)
+ * run in the library's own kernels.  The three heads are independent: the surrogate's v_rho, v_sigma
+ * are not exact derivatives of its f. */
+typedef struct kldi_mlp kldi_mlp;
+
+typedef struct {
+  uint64_t seed;                       /* parameter initialisation: U(+-1/sqrt(fan_in)), zero biases */
+} kldi_mlp_cfg;
+
+typedef struct {
+  int32_t epochs;                      /* passes over the training points                          */
+  int32_t batch;                       /* points per Adam step (> 0)                               */
+  double lr;                           /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8)        */
+  uint64_t seed;                       /* order of the points in each epoch                         */
+  int32_t xc;                          /* functional providing the targets (KLDI_XC_PBE or _PBE_X)  */
+  double rho_min;                      /* points below are not trained on and fall back later      */
+} kldi_train_cfg;
+
+kldi_status kldi_mlp_create(const kldi_mlp_cfg *cfg, kldi_mlp **out);
+kldi_status kldi_mlp_destroy(kldi_mlp *mlp);                       /* NULL is a no-op */
+
+/* Trains on n (rho, sigma) points (FP64 device arrays).  Points with rho < rho_min are dropped; the
+ * range box is the min/max of log rho and log sigma over the rest; targets are cfg->xc evaluated by
+ * the library, standardised by their mean and standard deviation.  loss_host[epochs] (host, may be
+ * NULL) receives the mean standardised squared error of each epoch.  Synchronises `stream`. */
+kldi_status kldi_mlp_train(kldi_mlp *mlp, const double *rho_dev, const double *sigma_dev, int64_t n,
+                           const kldi_train_cfg *cfg, double *loss_host, void *stream);
+
+/* f, v_rho, v_sigma at n points (FP64 device arrays) from the network where it covers the point
+ * (rho >= rho_min, features inside the box), else from the analytic functional it was trained on.
+ * used_dev[n] (device, may be NULL) receives 1 where the network was used. */
+kldi_status kldi_mlp_forward(const kldi_mlp *mlp, const double *rho_dev, const double *sigma_dev, int64_t n,
+                             double *f_dev, double *vrho_dev, double *vsigma_dev, int32_t *used_dev, void *stream);
+
+/* Loss and gradient of the training kernels for one batch, for checks: x_dev [n*2] features and
+ * t_dev [n*3] standardised targets (FP32 device arrays), 1 <= n <= 1048576.  *loss_host = mean
+ * squared error, grad_host[8707] = its gradient (host). */
+kldi_status kldi_mlp_loss_grad(kldi_mlp *mlp, const float *x_dev, const float *t_dev, int64_t n, double *loss_host,
+                               float *grad_host, void *stream);
+
+/* Host copies of the parameters (FP32 master, [8707]) and of the training statistics (box[4],
+ * tmean[3], tstd[3]); any pointer may be NULL.  set_params (host) overwrites the parameters. */
+kldi_status kldi_mlp_params(kldi_mlp *mlp, float *get_params, const float *set_params, double *box, double *tmean,
+                            double *tstd);
+
+/* Evaluations of a GGA plan then use the trained network in place of the analytic functional where
+ * it covers a point (NULL detaches).  The plan keeps a view: the network must outlive the plan's use. */
+kldi_status kldi_plan_attach_mlp(kldi_plan *plan, const kldi_mlp *mlp);
 
 /* Turns per-stage timing on (enable != 0) or off and clears the accumulated samples.  While on,
  * each kldi_eval records HIP events between its stages on its stream (up to 256 evaluations are

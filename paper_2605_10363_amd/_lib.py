@@ -42,7 +42,7 @@ class kldi_grid(ctypes.Structure):
 class kldi_opts(ctypes.Structure):
     _fields_ = [("t_b", ctypes.c_double), ("t_d", ctypes.c_double), ("rho_cut", ctypes.c_double),
                 ("grid_block", ctypes.c_int32), ("ao_block", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("xc", ctypes.c_int32), ("v_segment", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("xc", ctypes.c_int32), ("v_segment", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32)]
 
 
 class kldi_plan_info_t(ctypes.Structure):
@@ -50,12 +50,22 @@ class kldi_plan_info_t(ctypes.Structure):
                 ("n_blocks", ctypes.c_int64), ("n_candidate_tiles", ctypes.c_int64),
                 ("n_retained_tiles", ctypes.c_int64), ("retained_fraction", ctypes.c_double),
                 ("max_tiles_per_block", ctypes.c_int32), ("v_segment", ctypes.c_int32),
-                ("n_v_items", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("plan_ms", ctypes.c_double)]
+                ("n_v_items", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("n_grid_chunks", ctypes.c_int32),
+                ("plan_ms", ctypes.c_double)]
 
 
 class kldi_eval_stats_t(ctypes.Structure):
     _fields_ = [("n_pairs_x", ctypes.c_int64), ("n_pairs_v", ctypes.c_int64), ("gemm_flops", ctypes.c_double),
-                ("nonfinite_d", ctypes.c_int32)]
+                ("nonfinite_d", ctypes.c_int32), ("n_points_mlp", ctypes.c_int64)]
+
+
+class kldi_mlp_cfg(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64)]
+
+
+class kldi_train_cfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("xc", ctypes.c_int32), ("rho_min", ctypes.c_double)]
 
 
 def _sig(name, res, args):
@@ -80,12 +90,35 @@ kldi_eval_check = _sig("kldi_eval_check", ctypes.c_int,
 kldi_plan_timing = _sig("kldi_plan_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32])
 kldi_eval_timing = _sig("kldi_eval_timing", ctypes.c_int,
                         [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)])
+kldi_eval_grid = _sig("kldi_eval_grid", ctypes.c_int,
+                      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
+kldi_xc_eval = _sig("kldi_xc_eval", ctypes.c_int,
+                    [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
+kldi_mlp_create = _sig("kldi_mlp_create", ctypes.c_int, [ctypes.POINTER(kldi_mlp_cfg), ctypes.POINTER(ctypes.c_void_p)])
+kldi_mlp_destroy = _sig("kldi_mlp_destroy", ctypes.c_int, [ctypes.c_void_p])
+kldi_mlp_train = _sig("kldi_mlp_train", ctypes.c_int,
+                      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(kldi_train_cfg),
+                       ctypes.c_void_p, ctypes.c_void_p])
+kldi_mlp_forward = _sig("kldi_mlp_forward", ctypes.c_int,
+                        [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
+kldi_mlp_loss_grad = _sig("kldi_mlp_loss_grad", ctypes.c_int,
+                          [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                           ctypes.c_void_p, ctypes.c_void_p])
+kldi_mlp_params = _sig("kldi_mlp_params", ctypes.c_int,
+                       [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_void_p])
+kldi_plan_attach_mlp = _sig("kldi_plan_attach_mlp", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p])
 kldi_last_error = _sig("kldi_last_error", ctypes.c_char_p, [])
 kldi_version = _sig("kldi_version", ctypes.c_int32, [])
 
-EXPORTS = ["kldi_opts_default", "kldi_plan_create", "kldi_plan_destroy", "kldi_plan_info", "kldi_plan_structure",
-           "kldi_eval", "kldi_eval_check", "kldi_plan_timing", "kldi_eval_timing", "kldi_last_error", "kldi_version"]
-STAGES = ["dprep", "basis", "xtask", "vgemm", "vfinal"]
+EXPORTS = sorted(["kldi_opts_default", "kldi_plan_create", "kldi_plan_destroy", "kldi_plan_info",
+                  "kldi_plan_structure", "kldi_eval", "kldi_eval_check", "kldi_plan_timing", "kldi_eval_timing",
+                  "kldi_eval_grid", "kldi_xc_eval", "kldi_mlp_create", "kldi_mlp_destroy", "kldi_mlp_train",
+                  "kldi_mlp_forward", "kldi_mlp_loss_grad", "kldi_mlp_params", "kldi_plan_attach_mlp",
+                  "kldi_last_error", "kldi_version"])
+STAGES = ["dprep", "basis", "xgemm", "xfunc", "vgemm", "vfinal"]
 
 
 class KldiError(RuntimeError):

@@ -1,0 +1,246 @@
+// Device helpers shared by the HIP sources of libkldi: MFMA wrappers, wave reductions, the
+// workgroup prefix sum, basis-function evaluation and the exchange-correlation functionals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kldi_impl.h"
+
+namespace kldi {
+namespace dev {
+
+constexpr int NT = 256;          // threads per workgroup (4 waves of 64)
+constexpr int LDA_S = 33;        // LDS row stride of 32-wide row tiles
+constexpr int LDB_S = 130;       // LDS row stride of 128-wide rows
+constexpr int kMaxNp = 512;      // retained tiles per grid block handled by k_xgemm
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------------------------------
+// MFMA 16x16x4 wrappers.  Lane l supplies A[l%16][l/16] and B[l/16][l%16]; element v of the
+// accumulator of lane l is C[row(v,l)][l%16] -- row = 4v + l/16 for FP64, 4(l/16) + v for FP32
+// (measured on gfx950).
+// ------------------------------------------------------------------------------------------------
+template <class T>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int l) { return 4 * v + (l >> 4); }
+};
+template <>
+struct Mma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int l) { return 4 * (l >> 4) + v; }
+};
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
+  // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
+  // work items so neighbouring items (similar retained supports) share an L2
+  int64_t per = (n + 7) / 8;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Exclusive prefix sum of a 0/1 flag over the 256 threads of a workgroup (parallel addressing):
+// ballot + popcount within each wave, wave totals through LDS.  Returns the thread's slot and the
+// total in *total.  Must be called by all threads.
+__device__ __forceinline__ int block_scan(int flag, int *s_w, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned long long bal = __ballot(flag);
+  int before = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) s_w[w] = __popcll(bal);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int i = 0; i < 4; ++i) {
+    off += (i < w) ? s_w[i] : 0;
+    tot += s_w[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + before;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Basis functions (contracted cartesian Gaussians, N_rel-normalised components)
+// ------------------------------------------------------------------------------------------------
+static __constant__ int c_pow[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
+                                 {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
+static __constant__ double c_nrel[10] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.7320508075688772, 1.7320508075688772,
+                                  1.0, 1.7320508075688772, 1.0};
+
+__device__ __forceinline__ void pw4(double d, double *p) {
+  p[0] = 1.0;
+  p[1] = d;
+  p[2] = d * d;
+  p[3] = p[2] * d;
+}
+
+// Calls emit(a, value, gx, gy, gz) for every AO a (local row 0..31) of tile p at (x, y, z).
+template <bool GRAD, class F>
+__device__ __forceinline__ void for_tile_aos(const BasisDev &B, int p, double x, double y, double z, F &&emit) {
+  const int s0 = B.tile_sh[2 * p], s1 = B.tile_sh[2 * p + 1];
+  const int a_lo = p * kD, a_hi = a_lo + kD;
+  for (int s = s0; s < s1; ++s) {
+    const double dx = x - B.sh_xyz[3 * s], dy = y - B.sh_xyz[3 * s + 1], dz = z - B.sh_xyz[3 * s + 2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    double R = 0.0, R1 = 0.0;
+    for (int k = B.sh_prim[2 * s]; k < B.sh_prim[2 * s + 1]; ++k) {
+      const double e = B.pcoef[k] * exp(-B.pexp[k] * r2);
+      R += e;
+      if (GRAD) R1 -= 2.0 * B.pexp[k] * e;
+    }
+    const int l = B.sh_l[s], ao0 = B.sh_ao0[s];
+    const int cb = (l == 0) ? 0 : (l == 1 ? 1 : 4), nc = (l + 1) * (l + 2) / 2;
+    double px[4], py[4], pz[4];
+    pw4(dx, px);
+    pw4(dy, py);
+    pw4(dz, pz);
+    for (int c = 0; c < nc; ++c) {
+      const int ao = ao0 + c;
+      if (ao < a_lo || ao >= a_hi) continue;
+      const int lx = c_pow[cb + c][0], ly = c_pow[cb + c][1], lz = c_pow[cb + c][2];
+      const double nr = c_nrel[cb + c];
+      const double ang = px[lx] * py[ly] * pz[lz];
+      double gx = 0, gy = 0, gz = 0;
+      if (GRAD) {
+        gx = nr * ((lx ? lx * px[lx - 1] * py[ly] * pz[lz] : 0.0) * R + ang * dx * R1);
+        gy = nr * ((ly ? ly * px[lx] * py[ly - 1] * pz[lz] : 0.0) * R + ang * dy * R1);
+        gz = nr * ((lz ? lz * px[lx] * py[ly] * pz[lz - 1] : 0.0) * R + ang * dz * R1);
+      }
+      emit(ao - a_lo, nr * ang * R, gx, gy, gz);
+    }
+  }
+}
+
+// Value and gradient of one internal AO at (x, y, z); zero on padding rows.
+__device__ __forceinline__ void eval_ao(const BasisDev &B, int ao, double x, double y, double z, double &v,
+                                        double &gx, double &gy, double &gz) {
+  v = gx = gy = gz = 0.0;
+  const int s = B.ao_shell[ao];
+  if (s < 0) return;
+  const double dx = x - B.sh_xyz[3 * s], dy = y - B.sh_xyz[3 * s + 1], dz = z - B.sh_xyz[3 * s + 2];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  double R = 0.0, R1 = 0.0;
+  for (int k = B.sh_prim[2 * s]; k < B.sh_prim[2 * s + 1]; ++k) {
+    const double e = B.pcoef[k] * exp(-B.pexp[k] * r2);
+    R += e;
+    R1 -= 2.0 * B.pexp[k] * e;
+  }
+  const int cp = B.ao_comp[ao];
+  const int lx = cp & 3, ly = (cp >> 2) & 3, lz = (cp >> 4) & 3;
+  const double nr = ((lx == 1) + (ly == 1) + (lz == 1) == 2) ? 1.7320508075688772 : 1.0;
+  double px[4], py[4], pz[4];
+  pw4(dx, px);
+  pw4(dy, py);
+  pw4(dz, pz);
+  const double ang = px[lx] * py[ly] * pz[lz];
+  v = nr * ang * R;
+  gx = nr * ((lx ? lx * px[lx - 1] * py[ly] * pz[lz] : 0.0) * R + ang * dx * R1);
+  gy = nr * ((ly ? ly * px[lx] * py[ly - 1] * pz[lz] : 0.0) * R + ang * dy * R1);
+  gz = nr * ((lz ? lz * px[lx] * py[ly] * pz[lz - 1] : 0.0) * R + ang * dz * R1);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Functionals, FP64 (spin-unpolarised).  LDA: Slater exchange.  PBE: PBE exchange (kappa = 0.804,
+// mu = beta pi^2/3), PW92 correlation (unpolarised fit), PBE gradient correction H (phi = 1).
+// Returns f (energy per volume), v_rho = df/drho, v_sigma = df/dsigma.
+// ------------------------------------------------------------------------------------------------
+struct Xc {
+  double f, vr, vs;
+};
+
+__device__ __forceinline__ Xc xc_lda(double rho) {
+  const double cx = 0.73855876638202234;  // (3/4)(3/pi)^(1/3)
+  const double r13 = cbrt(rho);
+  return Xc{-cx * rho * r13, -(4.0 / 3.0) * cx * r13, 0.0};
+}
+
+__device__ __forceinline__ Xc xc_pbe_x(double rho, double sigma) {
+  const double cx = 0.73855876638202234, kappa = 0.804, mu = 0.21951497276451709;
+  const double r13 = cbrt(rho);
+  const double kf = cbrt(29.608813203268074 * rho);  // (3 pi^2 rho)^(1/3)
+  const double ds2 = 1.0 / (4.0 * kf * kf * rho * rho);
+  const double s2 = sigma * ds2;
+  const double den = 1.0 + mu * s2 / kappa;
+  const double F = 1.0 + kappa - kappa / den;
+  const double dF = mu / (den * den);
+  const double el = -cx * rho * r13;
+  return Xc{el * F, -cx * r13 * ((4.0 / 3.0) * F - (8.0 / 3.0) * s2 * dF), el * dF * ds2};
+}
+
+__device__ __forceinline__ Xc xc_pbe_c(double rho, double sigma) {
+  const double A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+  const double beta = 0.06672455060314922, gamma = 0.031090690869654895;  // (1 - ln 2)/pi^2
+  const double rs = cbrt(0.23873241463784300 / rho);                      // (3/(4 pi rho))^(1/3)
+  const double srs = sqrt(rs);
+  const double q0 = -2.0 * A * (1.0 + a1 * rs);
+  const double q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
+  const double dq1 = 2.0 * A * (0.5 * b1 / srs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs);
+  const double lg = log1p(1.0 / q1);
+  const double eps = q0 * lg;
+  const double deps_drs = -2.0 * A * a1 * lg - q0 * dq1 / (q1 * q1 + q1);
+  const double deps = deps_drs * (-rs / (3.0 * rho));
+  const double kf = cbrt(29.608813203268074 * rho);
+  const double ks2 = 4.0 * kf / 3.14159265358979324;
+  const double dt2 = 1.0 / (4.0 * ks2 * rho * rho);
+  const double t2 = sigma * dt2;
+  const double bg = beta / gamma;
+  const double Ac = bg / expm1(-eps / gamma);
+  const double dAc = Ac * Ac * exp(-eps / gamma) / beta;
+  const double u = Ac * t2;
+  const double den = 1.0 + u + u * u;
+  const double Q = (1.0 + u) / den;
+  const double dQ = -u * (2.0 + u) / (den * den);
+  const double y = bg * t2 * Q;
+  const double H = gamma * log1p(y);
+  const double dHy = gamma / (1.0 + y);
+  const double dyt2 = bg * (Q + t2 * dQ * Ac);
+  const double dyA = bg * t2 * dQ * t2;
+  const double dHr = dHy * (dyA * dAc * deps + dyt2 * (-7.0 / 3.0) * t2 / rho);
+  return Xc{rho * (eps + H), eps + H + rho * (deps + dHr), rho * dHy * dyt2 * dt2};
+}
+
+__device__ __forceinline__ Xc xc_eval(int xc, double rho, double sigma, double rho_cut) {
+  if (!(rho > rho_cut)) return Xc{0.0, 0.0, 0.0};
+  if (xc == KLDI_XC_LDA_X) return xc_lda(rho);
+  Xc x = xc_pbe_x(rho, sigma);
+  if (xc == KLDI_XC_PBE_X) return x;
+  Xc c = xc_pbe_c(rho, sigma);
+  return Xc{x.f + c.f, x.vr + c.vr, x.vs + c.vs};
+}
+
+struct FArgs {
+  GridDev g;
+  const int64_t *blk_item_off;   // [n_blocks+1] X work items of each block
+  int64_t blk0, item0;           // first block of this launch; first X item held by part
+  const double *part;
+  double *coef;                  // [n_pad][4]: w v_rho / 2, 2 w v_sigma grad rho
+  double *eblk;
+  double *rho_out;
+  double *sigma_out;             // optional: sigma in caller grid order
+  unsigned long long *counters;  // [3] counts points evaluated by the surrogate
+  double rho_cut;
+  int xc;
+  int gga;
+};
+
+}  // namespace dev
+}  // namespace kldi

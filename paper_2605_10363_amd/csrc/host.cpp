@@ -169,6 +169,7 @@ void validate(const kldi_basis *b, const kldi_grid *g, const kldi_opts *o) {
   if (o->prec != KLDI_PREC_FP64 && o->prec != KLDI_PREC_FP32) fail(KLDI_E_ARG, "unknown prec");
   if (o->xc != KLDI_XC_LDA_X && o->xc != KLDI_XC_PBE && o->xc != KLDI_XC_PBE_X) fail(KLDI_E_ARG, "unknown xc");
   if (o->v_segment < 0) fail(KLDI_E_ARG, "v_segment must be >= 0");
+  if (o->chunk_tiles < 0) fail(KLDI_E_ARG, "chunk_tiles must be >= 0");
 }
 
 void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opts *o, hipStream_t stream) {
@@ -379,44 +380,93 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
   S.ret_r = dev_upload(P, ret_r);
   S.idx_map = dev_upload(P, idx_map);
   S.bphi = dev_upload(P, P.bphi_h);
+  // X work items: (block, chunk of 4 consecutive retained tiles), block-major
+  {
+    std::vector<int> xr, xc;
+    std::vector<int64_t> boff(P.n_blocks + 1, 0);
+    for (int64_t r = 0; r < P.n_blocks; ++r) {
+      const int np = int(P.blk_off_h[r + 1] - P.blk_off_h[r]);
+      for (int c = 0; kChunk * c < np; ++c) {
+        xr.push_back(int(r));
+        xc.push_back(c);
+      }
+      boff[r + 1] = int64_t(xr.size());
+    }
+    P.n_xitems = int64_t(xr.size());
+    P.xit_r = dev_upload(P, xr);
+    P.xit_c = dev_upload(P, xc);
+    P.blk_item_off = dev_upload(P, boff);
+    P.blk_item_off_h = boff;
+  }
 
   // ---- Vxc work list: (row chunk, column chunk, segment of grid blocks)
   const int nc = P.n_chunks;
   const int npairs = P.gga ? nc * nc : nc * (nc + 1) / 2;
   P.n_pairs = npairs;
+  auto pair_index = [&](int pc, int qc) { return P.gga ? pc * nc + qc : pc * nc - pc * (pc - 1) / 2 + (qc - pc); };
+  // chunks present at each block
+  std::vector<std::vector<int>> blk_chunks(P.n_blocks);
+  for (int64_t r = 0; r < P.n_blocks; ++r)
+    for (int64_t k = P.blk_off_h[r]; k < P.blk_off_h[r + 1]; ++k) {
+      const int c = P.ret_p_h[k] / kChunk;
+      if (blk_chunks[r].empty() || blk_chunks[r].back() != c) blk_chunks[r].push_back(c);
+    }
+  // work items of a segment length: the chunk pairs that co-occur at some block of the segment
+  std::vector<int> stamp(npairs, -1);
+  auto visit_items = [&](int seg, auto &&emit) {
+    const int64_t nseg = (P.n_blocks + seg - 1) / seg;
+    for (int64_t sg = 0; sg < nseg; ++sg) {
+      const int r0 = int(sg * seg), r1 = int(std::min<int64_t>(P.n_blocks, (sg + 1) * seg));
+      std::vector<int> act;
+      for (int r = r0; r < r1; ++r)
+        for (int pc : blk_chunks[r])
+          for (int qc : blk_chunks[r]) {
+            if (!P.gga && qc < pc) continue;
+            const int pi = pair_index(pc, qc);
+            if (stamp[pi] != int(sg)) {
+              stamp[pi] = int(sg);
+              act.push_back(pi);
+            }
+          }
+      std::sort(act.begin(), act.end());
+      for (int pi : act) emit(pi, r0, r1);
+    }
+    std::fill(stamp.begin(), stamp.end(), -1);
+  };
   int seg = o->v_segment;
   if (seg <= 0) {
-    int64_t nseg = std::max<int64_t>(1, (4096 + npairs - 1) / npairs);
-    nseg = std::min<int64_t>(nseg, std::max<int64_t>(1, P.n_blocks / 16));
-    // partial buffers: at most ~2 GiB
-    int64_t cap = std::max<int64_t>(1, (int64_t(2) << 30) / (int64_t(npairs) * 16384 * 8));
-    nseg = std::min(nseg, cap);
-    seg = int((P.n_blocks + nseg - 1) / nseg);
+    // shortest segment (better L2 sharing among the items of a segment) whose FP64 partials fit a
+    // budget of min(16 GiB, 1/5 of free device memory)
+    size_t fr0 = 0, tot0 = 0;
+    check_hip(hipMemGetInfo(&fr0, &tot0), "hipMemGetInfo");
+    const size_t budget = std::min<size_t>(size_t(16) << 30, fr0 / 5);
+    for (seg = 16;; seg *= 2) {
+      int64_t n = 0;
+      visit_items(seg, [&](int, int, int) { ++n; });
+      if (size_t(n) * 16384 * 8 <= budget || seg >= P.n_blocks) break;
+    }
   }
   P.v_segment = seg;
-  const int64_t nseg = (P.n_blocks + seg - 1) / seg;
   std::vector<std::vector<int>> pair_lists(npairs);
-  auto pair_index = [&](int pc, int qc) { return P.gga ? pc * nc + qc : pc * nc - pc * (pc - 1) / 2 + (qc - pc); };
-  std::vector<uint8_t> present(nc);
-  for (int64_t sg = 0; sg < nseg; ++sg) {
-    int r0 = int(sg * seg), r1 = int(std::min<int64_t>(P.n_blocks, (sg + 1) * seg));
-    std::fill(present.begin(), present.end(), 0);
-    for (int64_t k = P.blk_off_h[r0]; k < P.blk_off_h[r1]; ++k) present[P.ret_p_h[k] / kChunk] = 1;
-    for (int pc = 0; pc < nc; ++pc) {
-      if (!present[pc]) continue;
-      for (int qc = P.gga ? 0 : pc; qc < nc; ++qc) {
-        if (!present[qc]) continue;
-        pair_lists[pair_index(pc, qc)].push_back(int(P.items_h.size()));
-        P.items_h.push_back(VItem{pc, qc, r0, r1});
-      }
-    }
-  }
-  std::vector<int> pair_ptr(npairs + 1, 0), pair_items, pair_pq(2 * npairs);
+  std::vector<int> pair_pc(npairs), pair_qc(npairs);
   for (int pc = 0; pc < nc; ++pc)
     for (int qc = P.gga ? 0 : pc; qc < nc; ++qc) {
-      pair_pq[2 * pair_index(pc, qc)] = pc;
-      pair_pq[2 * pair_index(pc, qc) + 1] = qc;
+      pair_pc[pair_index(pc, qc)] = pc;
+      pair_qc[pair_index(pc, qc)] = qc;
     }
+  const int64_t n_segs = (P.n_blocks + seg - 1) / seg;
+  std::vector<int64_t> seg_item_off(n_segs + 1, 0);
+  visit_items(seg, [&](int pi, int r0, int r1) {
+    pair_lists[pi].push_back(int(P.items_h.size()));
+    P.items_h.push_back(VItem{pair_pc[pi], pair_qc[pi], r0, r1, pi, 0});
+    seg_item_off[r0 / seg + 1] = int64_t(P.items_h.size());
+  });
+  for (int64_t sg = 1; sg <= n_segs; ++sg) seg_item_off[sg] = std::max(seg_item_off[sg], seg_item_off[sg - 1]);
+  std::vector<int> pair_ptr(npairs + 1, 0), pair_items, pair_pq(2 * npairs);
+  for (int i = 0; i < npairs; ++i) {
+    pair_pq[2 * i] = pair_pc[i];
+    pair_pq[2 * i + 1] = pair_qc[i];
+  }
   for (int i = 0; i < npairs; ++i) {
     pair_ptr[i + 1] = pair_ptr[i] + int(pair_lists[i].size());
     pair_items.insert(pair_items.end(), pair_lists[i].begin(), pair_lists[i].end());
@@ -425,33 +475,81 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
   P.pair_ptr = dev_upload(P, pair_ptr);
   P.pair_items = dev_upload(P, pair_items);
   P.pair_pq = dev_upload(P, pair_pq);
+  {
+    // per (block, chunk): position in S_r of the chunk's first retained tile, and its 4-bit mask
+    std::vector<int> cinfo(size_t(P.n_blocks) * nc, 0);
+    for (int64_t r = 0; r < P.n_blocks; ++r)
+      for (int64_t k = P.blk_off_h[r + 1] - 1; k >= P.blk_off_h[r]; --k) {
+        const int p = P.ret_p_h[k], c = p / kChunk;
+        int &ci = cinfo[size_t(r) * nc + c];
+        ci = (int(k - P.blk_off_h[r]) << 4) | (ci & 15) | (1 << (p % kChunk));
+      }
+    P.cinfo = dev_upload(P, cinfo);
+  }
   P.ao_perm_d = dev_upload(P, P.ao_perm);
 
-  // ---- per-evaluation workspaces
+  // ---- grid chunks: whole Vxc segments whose retained tiles fit the Phi / Z workspaces
   const size_t esz = (o->prec == KLDI_PREC_FP64) ? 8 : 4;
-  size_t need = size_t(P.n_ret) * 4096 * esz * 2 + size_t(P.items_h.size()) * 16384 * 8 +
-                size_t(nc * kChunk * kD) * size_t(nc * kChunk * kD) * 8;
-  size_t fr = 0, tot = 0;
-  check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
-  if (need + (size_t(256) << 20) > fr)
-    fail(KLDI_E_OOM, "workspaces need " + std::to_string(need >> 20) + " MiB, " + std::to_string(fr >> 20) +
-                         " MiB free");
+  const size_t fixed = size_t(P.items_h.size()) * 16384 * 8 + size_t(nc * kChunk * kD) * size_t(nc * kChunk * kD) * 8 +
+                       size_t(P.n_pad) * 32 + size_t(P.n_ret) * 8 + size_t(P.n_tiles) * P.n_tiles * (1024 * esz + 8);
+  const size_t per_tile = 2 * 4096 * esz;       // Phi + Z
+  int64_t cap = o->chunk_tiles;
+  {
+    size_t fr = 0, tot = 0;
+    check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    const size_t reserve = size_t(1) << 30;
+    if (fixed + reserve > fr) fail(KLDI_E_OOM, "fixed workspaces need " + std::to_string(fixed >> 20) + " MiB");
+    const int64_t fit = int64_t((fr - fixed - reserve) * 0.8 / (per_tile + 4096));
+    if (cap <= 0 || cap > fit) cap = fit;
+  }
+  {
+    int64_t s0 = 0;
+    while (s0 < n_segs) {
+      int64_t s1 = s0 + 1;
+      auto ret_of = [&](int64_t a, int64_t b) {
+        return P.blk_off_h[std::min<int64_t>(P.n_blocks, b * seg)] - P.blk_off_h[a * seg];
+      };
+      while (s1 < n_segs && ret_of(s0, s1 + 1) <= cap) ++s1;
+      GridChunk C;
+      C.blk0 = s0 * seg;
+      C.blk1 = std::min<int64_t>(P.n_blocks, s1 * seg);
+      C.ret0 = P.blk_off_h[C.blk0];
+      C.ret1 = P.blk_off_h[C.blk1];
+      C.xit0 = P.blk_item_off_h[C.blk0];
+      C.xit1 = P.blk_item_off_h[C.blk1];
+      C.vit0 = seg_item_off[s0];
+      C.vit1 = seg_item_off[s1];
+      P.chunks_h.push_back(C);
+      s0 = s1;
+    }
+  }
+  int64_t max_ret = 0, max_xit = 0, max_blk = 0;
+  for (const GridChunk &C : P.chunks_h) {
+    max_ret = std::max(max_ret, C.ret1 - C.ret0);
+    max_xit = std::max(max_xit, C.xit1 - C.xit0);
+    max_blk = std::max(max_blk, C.blk1 - C.blk0);
+  }
   EvalDev &E = P.ev;
   size_t nt2 = size_t(P.n_tiles) * P.n_tiles;
   E.Dt = (esz == 8) ? (void *)dev_alloc<double>(P, nt2 * 1024) : (void *)dev_alloc<float>(P, nt2 * 1024);
   E.amax = dev_alloc<double>(P, nt2);
   if (esz == 8) {
-    E.phi = dev_alloc<double>(P, size_t(P.n_ret) * 4096);
-    E.zws = dev_alloc<double>(P, size_t(P.n_ret) * 4096);
+    E.phi = dev_alloc<double>(P, size_t(max_ret) * 4096);
+    E.zws = dev_alloc<double>(P, size_t(max_ret) * 4096);
   } else {
-    E.phi = dev_alloc<float>(P, size_t(P.n_ret) * 4096);
-    E.zws = dev_alloc<float>(P, size_t(P.n_ret) * 4096);
+    E.phi = dev_alloc<float>(P, size_t(max_ret) * 4096);
+    E.zws = dev_alloc<float>(P, size_t(max_ret) * 4096);
   }
   E.zmax = dev_alloc<double>(P, P.n_ret);
+  E.xpart = dev_alloc<double>(P, size_t(max_xit) * 4 * kG);
+  E.coef = dev_alloc<double>(P, size_t(P.n_pad) * 4);
   E.eblk = dev_alloc<double>(P, P.n_blocks);
   E.vpart = dev_alloc<double>(P, P.items_h.size() * 16384);
+  E.vflag = dev_alloc<int>(P, P.items_h.size());
+  E.vmask = dev_alloc<unsigned short>(P, size_t(max_blk) * npairs);
   E.mfull = dev_alloc<double>(P, size_t(nc * kChunk * kD) * size_t(nc * kChunk * kD));
   E.counters = dev_alloc<unsigned long long>(P, 4);
+  E.escratch = dev_alloc<double>(P, 1);
   check_hip(hipMemsetAsync(E.counters, 0, 4 * sizeof(unsigned long long), stream), "memset");
   check_hip(hipStreamSynchronize(stream), "plan sync");
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -479,10 +577,6 @@ kldi_status guarded(F &&f) {
 
 }  // namespace
 }  // namespace kldi
-
-struct kldi_plan {
-  kldi::Plan impl;
-};
 
 using kldi::Plan;
 
@@ -553,6 +647,7 @@ kldi_status kldi_plan_info(const kldi_plan *plan, kldi_plan_info_t *out) {
   out->v_segment = P.v_segment;
   out->n_v_items = int64_t(P.items_h.size());
   out->workspace_bytes = int64_t(P.bytes);
+  out->n_grid_chunks = int32_t(P.chunks_h.size());
   out->plan_ms = P.plan_ms;
   return KLDI_OK;
 }
@@ -592,8 +687,9 @@ kldi_status kldi_eval(kldi_plan *plan, const double *D_dev, double *rho_dev, dou
       ev = &plan->impl.events[size_t(P.n_timed % kldi::kTimingSlots) * (KLDI_N_STAGES + 1)];
       plan->impl.n_timed++;
     }
-    kldi::check_hip(kldi::launch_eval(P, D_dev, rho_dev, exc_dev, vxc_dev, static_cast<hipStream_t>(stream), ev),
-                    "eval launch");
+    kldi::check_hip(
+        kldi::launch_eval(P, D_dev, rho_dev, nullptr, exc_dev, vxc_dev, static_cast<hipStream_t>(stream), ev),
+        "eval launch");
   });
 }
 
@@ -611,6 +707,7 @@ kldi_status kldi_eval_check(kldi_plan *plan, kldi_eval_stats_t *out, void *strea
   out->n_pairs_x = int64_t(c[0]);
   out->n_pairs_v = int64_t(c[1]);
   out->gemm_flops = 2.0 * kldi::kD * kldi::kD * kldi::kG * double(c[0] + c[1]);
+  out->n_points_mlp = int64_t(c[3]);
   out->nonfinite_d = c[2] ? 1 : 0;
   if (c[2]) {
     kldi::set_error("D holds a non-finite entry");
@@ -657,6 +754,36 @@ kldi_status kldi_eval_timing(kldi_plan *plan, double *stage_ms, int32_t *n_evals
       }
     }
     for (int s = 0; s < KLDI_N_STAGES; ++s) stage_ms[s] /= n;
+  });
+}
+
+kldi_status kldi_eval_grid(kldi_plan *plan, const double *D_dev, double *rho_dev, double *sigma_dev, void *stream) {
+  if (!plan || !D_dev || (!rho_dev && !sigma_dev)) {
+    kldi::set_error("plan and D must not be NULL; one of rho, sigma must be given");
+    return KLDI_E_ARG;
+  }
+  return kldi::guarded([&] {
+    const Plan &P = plan->impl;
+    kldi::check_hip(hipSetDevice(P.device), "hipSetDevice");
+    // E_xc of this call goes to the plan's per-block partials only
+    kldi::check_hip(kldi::launch_eval(P, D_dev, rho_dev, sigma_dev, P.ev.escratch, nullptr,
+                                      static_cast<hipStream_t>(stream), nullptr),
+                    "eval launch");
+  });
+}
+
+kldi_status kldi_xc_eval(int32_t xc, const double *rho_dev, const double *sigma_dev, int64_t n, double rho_cut,
+                         double *f_dev, double *vrho_dev, double *vsigma_dev, void *stream) {
+  if (n < 0 || !rho_dev || !f_dev || !vrho_dev || (xc != KLDI_XC_LDA_X && (!sigma_dev || !vsigma_dev)) ||
+      (xc != KLDI_XC_LDA_X && xc != KLDI_XC_PBE && xc != KLDI_XC_PBE_X) || !(rho_cut >= 0)) {
+    kldi::set_error("bad arguments to kldi_xc_eval");
+    return KLDI_E_ARG;
+  }
+  return kldi::guarded([&] {
+    kldi::check_hip(kldi::launch_xc_arrays(xc, rho_dev, xc == KLDI_XC_LDA_X ? nullptr : sigma_dev, n, rho_cut, f_dev,
+                                           vrho_dev, xc == KLDI_XC_LDA_X ? nullptr : vsigma_dev,
+                                           static_cast<hipStream_t>(stream)),
+                    "xc launch");
   });
 }
 

@@ -22,7 +22,7 @@ class Plan:
     """
 
     def __init__(self, atom_xyz, basis, grid_xyz, weights, point_atom, xc="lda", prec="fp64", t_b=1e-10,
-                 t_d=1e-10, rho_cut=1e-14, grid_block=128, ao_block=32, v_segment=0, stream=None):
+                 t_d=1e-10, rho_cut=1e-14, grid_block=128, ao_block=32, v_segment=0, chunk_tiles=0, stream=None):
         self._h = ctypes.c_void_p()
         self._keep = [np.ascontiguousarray(atom_xyz, np.float64),
                       np.ascontiguousarray(basis.shell_atom, np.int32),
@@ -41,7 +41,7 @@ class Plan:
         L.kldi_opts_default(ctypes.byref(o))
         o.t_b, o.t_d, o.rho_cut = float(t_b), float(t_d), float(rho_cut)
         o.grid_block, o.ao_block = int(grid_block), int(ao_block)
-        o.prec, o.xc, o.v_segment = L.PREC[prec], L.XC[xc], int(v_segment)
+        o.prec, o.xc, o.v_segment, o.chunk_tiles = L.PREC[prec], L.XC[xc], int(v_segment), int(chunk_tiles)
         self.xc, self.prec = xc, prec
         L.check(L.kldi_plan_create(ctypes.byref(b), ctypes.byref(g), ctypes.byref(o), _stream_handle(stream),
                                    ctypes.byref(self._h)), "kldi_plan_create")
@@ -82,6 +82,20 @@ class Plan:
                             _stream_handle(stream)), "kldi_eval")
         return r, e, v
 
+    def eval_grid(self, D, stream=None):
+        """rho and sigma on the grid (device tensors, caller order) -- kldi_eval_grid."""
+        if not (isinstance(D, torch.Tensor) and D.is_cuda and D.dtype == torch.float64 and D.is_contiguous()):
+            raise TypeError("D must be a contiguous float64 CUDA tensor")
+        rho = torch.empty(self.n_points, dtype=torch.float64, device=D.device)
+        sigma = torch.empty(self.n_points, dtype=torch.float64, device=D.device)
+        L.check(L.kldi_eval_grid(self._h, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(rho.data_ptr()),
+                                 ctypes.c_void_p(sigma.data_ptr()), _stream_handle(stream)), "kldi_eval_grid")
+        return rho, sigma
+
+    def attach_mlp(self, mlp):
+        L.check(L.kldi_plan_attach_mlp(self._h, mlp._h if mlp is not None else None), "kldi_plan_attach_mlp")
+        self._mlp = mlp
+
     def check(self, stream=None) -> dict:
         s = L.kldi_eval_stats_t()
         st = L.kldi_eval_check(self._h, ctypes.byref(s), _stream_handle(stream))
@@ -113,3 +127,78 @@ class Plan:
     def from_problem(cls, p, **kw):
         kw.setdefault("xc", p.xc)
         return cls(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, **kw)
+
+
+def xc_eval(xc, rho, sigma=None, rho_cut=0.0, stream=None):
+    """The library's functional on device arrays (kldi_xc_eval): returns (f, v_rho, v_sigma)."""
+    n = rho.numel()
+    f = torch.empty_like(rho)
+    vr = torch.empty_like(rho)
+    vs = torch.empty_like(rho) if sigma is not None else None
+    L.check(L.kldi_xc_eval(L.XC[xc], ctypes.c_void_p(rho.data_ptr()),
+                           ctypes.c_void_p(sigma.data_ptr() if sigma is not None else 0), n, float(rho_cut),
+                           ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(vr.data_ptr()),
+                           ctypes.c_void_p(vs.data_ptr() if vs is not None else 0), _stream_handle(stream)),
+            "kldi_xc_eval")
+    return f, vr, vs
+
+
+class Mlp:
+    """kldi_mlp_*: the functional surrogate (2-64-64-64-3 SiLU), trained and run by libkldi."""
+
+    N_PARAMS = 8707
+
+    def __init__(self, seed=0):
+        self._h = ctypes.c_void_p()
+        cfg = L.kldi_mlp_cfg(int(seed))
+        L.check(L.kldi_mlp_create(ctypes.byref(cfg), ctypes.byref(self._h)), "kldi_mlp_create")
+
+    def params(self, set_params=None):
+        get = np.empty(self.N_PARAMS, np.float32)
+        box = np.empty(4)
+        tm = np.empty(3)
+        ts = np.empty(3)
+        sp = None
+        if set_params is not None:
+            sp = np.ascontiguousarray(set_params, np.float32)
+        L.check(L.kldi_mlp_params(self._h, get.ctypes.data, sp.ctypes.data if sp is not None else None, box.ctypes.data,
+                                  tm.ctypes.data, ts.ctypes.data), "kldi_mlp_params")
+        return get, box, tm, ts
+
+    def loss_grad(self, x, t, stream=None):
+        """x: float32 CUDA [n, 2] features, t: float32 CUDA [n, 3] standardised targets."""
+        g = np.empty(self.N_PARAMS, np.float32)
+        loss = ctypes.c_double()
+        L.check(L.kldi_mlp_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()), x.shape[0],
+                                     ctypes.byref(loss), g.ctypes.data, _stream_handle(stream)), "kldi_mlp_loss_grad")
+        return loss.value, g
+
+    def train(self, rho, sigma, epochs=10, batch=65536, lr=2e-3, seed=1, xc="pbe", rho_min=1e-8, stream=None):
+        cfg = L.kldi_train_cfg(int(epochs), int(batch), float(lr), int(seed), L.XC[xc], float(rho_min))
+        losses = np.zeros(max(int(epochs), 1))
+        L.check(L.kldi_mlp_train(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(sigma.data_ptr()),
+                                 rho.numel(), ctypes.byref(cfg), losses.ctypes.data, _stream_handle(stream)),
+                "kldi_mlp_train")
+        return losses[:epochs]
+
+    def forward(self, rho, sigma, stream=None):
+        f = torch.empty_like(rho)
+        vr = torch.empty_like(rho)
+        vs = torch.empty_like(rho)
+        used = torch.empty(rho.numel(), dtype=torch.int32, device=rho.device)
+        L.check(L.kldi_mlp_forward(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(sigma.data_ptr()),
+                                   rho.numel(), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(vr.data_ptr()),
+                                   ctypes.c_void_p(vs.data_ptr()), ctypes.c_void_p(used.data_ptr()),
+                                   _stream_handle(stream)), "kldi_mlp_forward")
+        return f, vr, vs, used
+
+    def close(self):
+        if self._h:
+            L.kldi_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,129 @@
+"""GPU: the learned functional surrogate and the auxiliary entry points, through the C ABI, against the
+FP64 oracle (oracle.mlp, oracle.functionals, oracle.exc)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import functionals as fx
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_10363_amd import plan as m
+    return m
+
+
+def test_xc_eval_arrays_match_oracle(mod):
+    rng = np.random.default_rng(3)
+    rho = 10 ** rng.uniform(-12, 2, 5000)
+    sig = rho ** (8 / 3) * 10 ** rng.uniform(-4, 2, 5000)
+    for xc in ("lda", "pbe", "pbe_x"):
+        f, vr, vs = mod.xc_eval(xc, torch.from_numpy(rho).cuda(), torch.from_numpy(sig).cuda(), 1e-14)
+        ef, evr, evs = fx.evaluate(xc, rho, sig, 1e-14)
+        assert np.allclose(f.cpu().numpy(), ef, rtol=1e-12, atol=0)
+        assert np.allclose(vr.cpu().numpy(), evr, rtol=1e-12, atol=0)
+        if xc != "lda":
+            assert np.allclose(vs.cpu().numpy(), evs, rtol=1e-11, atol=0)
+
+
+def test_eval_grid_rho_and_sigma(mod):
+    p = synth.tiny_problem(n_atoms=4, n_rad=14, n_ang=38, n_occ=4, xc="pbe", seed=61, box_A=4.0)
+    ref = oracle.eval_exc(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.D, "pbe", want_v=False)
+    plan = mod.Plan.from_problem(p, xc="pbe", t_b=0.0, t_d=0.0)
+    rho, sigma = plan.eval_grid(torch.from_numpy(p.D).cuda())
+    assert np.allclose(rho.cpu().numpy(), ref["rho"], rtol=1e-12, atol=1e-300)
+    assert np.allclose(sigma.cpu().numpy(), ref["sigma"], rtol=1e-11, atol=1e-300)
+    plan.close()
+
+
+def test_training_kernel_gradient_matches_fp64_oracle(mod):
+    rng = np.random.default_rng(4)
+    net = mod.Mlp(seed=11)
+    theta = omlp.init_params(rng) + 0.05 * rng.normal(size=omlp.N_PARAMS)
+    net.params(set_params=theta.astype(np.float32))
+    th32 = theta.astype(np.float32).astype(np.float64)
+    for n in (1, 63, 64, 1000, 4099):
+        x = rng.uniform(-1, 1, size=(n, 2)).astype(np.float32)
+        t = rng.normal(size=(n, 3)).astype(np.float32)
+        L, g = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+        Lr, gr = omlp.loss_and_grad(th32, x.astype(np.float64), t.astype(np.float64))
+        print("n=%d loss %.8f oracle %.8f  max|dg| %.2e  max|g| %.2e" % (n, L, Lr, np.abs(g - gr).max(),
+                                                                       np.abs(gr).max()), flush=True)
+        assert abs(L - Lr) <= 1e-5 * Lr
+        assert np.abs(g - gr).max() <= 1e-4 * np.abs(gr).max()
+    net.close()
+
+
+@pytest.fixture(scope="module")
+def trained(mod):
+    """A surrogate trained on the (rho, sigma) points of the 12-atom workload's grid with PBE geometry."""
+    p = synth.make_problem(0)
+    plan = mod.Plan.from_problem(p, xc="pbe")
+    rho, sigma = plan.eval_grid(torch.from_numpy(p.D).cuda())
+    net = mod.Mlp(seed=5)
+    losses = net.train(rho, sigma, epochs=40, batch=8192, lr=3e-3, seed=9, xc="pbe", rho_min=1e-8)
+    print("training loss per epoch:", np.array2string(losses[[0, 9, 19, 39]], precision=5), flush=True)
+    return p, plan, net, rho, sigma, losses
+
+
+def test_training_reduces_loss(trained):
+    p, plan, net, rho, sigma, losses = trained
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.05 * losses[0]
+
+
+def test_inference_matches_oracle_forward_and_falls_back(mod, trained):
+    p, plan, net, rho, sigma, losses = trained
+    theta, box, tm, ts = net.params()
+    r = rho.cpu().numpy()
+    s = sigma.cpu().numpy()
+    f, vr, vs, used = net.forward(rho, sigma)
+    f, vr, vs, used = f.cpu().numpy(), vr.cpu().numpy(), vs.cpu().numpy(), used.cpu().numpy().astype(bool)
+    assert np.array_equal(used, r >= 1e-8)             # the box is the training range
+    # network points: BF16 inference against the FP64 oracle network with the same parameters
+    x = omlp.features(r[used], s[used], box)
+    y, _ = omlp.forward(theta.astype(np.float64), x)
+    yg = (omlp.targets(r[used], f[used], vr[used], vs[used]) - tm) / ts
+    dy = np.abs(yg - y)
+    print("inference |dy| max %.3e mean %.3e (standardised heads)" % (dy.max(), dy.mean()), flush=True)
+    assert dy.max() < 0.15 and dy.mean() < 0.02
+    # fallback points are the analytic functional
+    af, avr, avs = fx.evaluate("pbe", r[~used], s[~used], 0.0)
+    assert np.allclose(f[~used], af, rtol=1e-12, atol=1e-300)
+    assert np.allclose(vr[~used], avr, rtol=1e-12, atol=1e-300)
+
+
+def test_attached_surrogate_in_evaluation(mod, trained):
+    """The trained network replaces the analytic PBE inside kldi_eval; report what it gains."""
+    p, plan, net, rho, sigma, losses = trained
+    D = torch.from_numpy(p.D).cuda()
+    _, e_an, v_an = plan.eval(D)
+    plan.timing(True)
+    for _ in range(3):
+        plan.eval(D)
+    st_an, _ = plan.stage_ms()
+    plan.attach_mlp(net)
+    _, e_ml, v_ml = plan.eval(D)
+    stats = plan.check()
+    plan.timing(True)
+    for _ in range(3):
+        plan.eval(D)
+    st_ml, _ = plan.stage_ms()
+    E_an, E_ml = float(e_an.item()), float(e_ml.item())
+    dV = float((v_ml - v_an).abs().max().item())
+    frac = stats["n_points_mlp"] / p.n_points
+    print("surrogate: E %.8f vs analytic %.8f (rel %.2e), max|dV| %.2e, network on %.1f%% of points, "
+          "functional stage %.3f ms vs %.3f ms" % (E_ml, E_an, abs(E_ml - E_an) / abs(E_an), dV, 100 * frac,
+                                                   st_ml["xfunc"], st_an["xfunc"]), flush=True)
+    assert abs(E_ml - E_an) < 2e-2 * abs(E_an)
+    assert 0.2 < frac <= 1.0
+    plan.attach_mlp(None)
+    _, e_back, _ = plan.eval(D)
+    assert float(e_back.item()) == E_an

@@ -147,3 +147,23 @@ def test_rho_only_and_no_vxc(Plan):
     assert abs(float(exc.item()) - ref["E"]) <= 1e-12 * abs(ref["E"])
     assert np.abs(rho.cpu().numpy() - ref["rho"]).max() <= 1e-12 * np.abs(ref["rho"]).max()
     plan.close()
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_grid_chunks_give_identical_results(Plan, cfg0, xc):
+    """Processing the grid in several chunks of whole Vxc segments (small Phi/Z workspaces) must give
+    bit-identical results to one chunk: the same work items run, and every sum keeps its order."""
+    p = cfg0
+    D = torch.from_numpy(p.D).cuda()
+    outs = []
+    for ct in (0, 40):
+        plan = Plan.from_problem(p, xc=xc, v_segment=16, chunk_tiles=ct)
+        info = plan.info()
+        print("chunk_tiles=%d -> %d grid chunks" % (ct, info["n_grid_chunks"]), flush=True)
+        outs.append(([t.cpu().numpy().copy() for t in plan.eval(D)], plan.check(), info["n_grid_chunks"]))
+        plan.close()
+    (a, sa, na), (b, sb, nb) = outs
+    assert na == 1 and nb > 1
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert (sa["n_pairs_x"], sa["n_pairs_v"]) == (sb["n_pairs_x"], sb["n_pairs_v"])
