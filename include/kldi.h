@@ -95,6 +95,14 @@ typedef struct {
   const int32_t *point_atom;     /* [n_points], 0 <= atom < n_atoms                               */
 } kldi_grid;
 
+/* How the block-GEMM stages distribute their work items (tasks of Sec. III-D) over the GPU. */
+typedef enum {
+  KLDI_SCHED_GRID = 0,      /* one workgroup per work item; the hardware dispatcher balances      */
+  KLDI_SCHED_QUEUE = 1      /* persistent workgroups pull items from 8 per-XCD queues (items of a
+                               queue share L2; each queue ordered by decreasing estimated cost) and
+                               take from the other queues when theirs is empty                     */
+} kldi_schedule;
+
 typedef struct {
   double t_b;                    /* block-retention threshold (eq. block_filter_A), >= 0          */
   double t_d;                    /* block-pair execution threshold (eq. block_pair_filter), >= 0  */
@@ -103,9 +111,11 @@ typedef struct {
   int32_t ao_block;              /* d, AOs per tile; this build supports 32                       */
   int32_t prec;                  /* kldi_prec                                                     */
   int32_t xc;                    /* kldi_xc                                                       */
-  int32_t v_segment;             /* grid blocks per Vxc accumulation segment; 0 = chosen by plan  */
+  int32_t v_segment;             /* grid blocks per Vxc work item (the K extent of its tile);
+                                    0 = chosen by the plan                                         */
   int32_t chunk_tiles;           /* max retained tiles whose Phi/Z are held at once (the grid is
                                     processed in chunks of whole Vxc segments); 0 = fit to memory */
+  int32_t schedule;              /* kldi_schedule                                                 */
 } kldi_opts;
 
 typedef struct kldi_plan kldi_plan;
@@ -122,6 +132,10 @@ typedef struct {
   int64_t workspace_bytes;             /* device bytes held by the plan                           */
   int32_t n_grid_chunks;               /* chunks of grid blocks per evaluation                    */
   double plan_ms;                      /* wall time of kldi_plan_create                           */
+  int32_t n_mol;                       /* molecules (1 for kldi_plan_create)                      */
+  int32_t schedule;                    /* kldi_schedule in use                                    */
+  int32_t graph;                       /* 1 if evaluations replay a captured graph                */
+  int64_t n_x_items;                   /* X = D Phi work items (grid block x chunk of 4 tiles)     */
 } kldi_plan_info_t;
 
 typedef struct {
@@ -143,7 +157,8 @@ typedef enum {
   KLDI_N_STAGES = 6
 } kldi_stage;
 
-/* Fills *opts with defaults: t_b = t_d = 1e-10, rho_cut = 1e-14, G = 128, d = 32, FP64, LDA. */
+/* Fills *opts with defaults: t_b = t_d = 1e-10, rho_cut = 1e-14, G = 128, d = 32, FP64, LDA,
+ * v_segment and chunk_tiles chosen by the plan, KLDI_SCHED_GRID. */
 void kldi_opts_default(kldi_opts *opts);
 
 /* Builds the geometry-level structure reused across evaluations (Sec. III-B.3: reordering and
@@ -158,13 +173,50 @@ void kldi_opts_default(kldi_opts *opts);
 kldi_status kldi_plan_create(const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts,
                              void *stream, kldi_plan **out);
 
+/* Batching form: one plan over n_mol independent molecules (basis[m], grid[m], host arrays of n_mol
+ * structs, each as for kldi_plan_create; opts shared).  All molecules live in one index space: every
+ * stage of kldi_eval runs once over all of them (one launch per stage), so uneven molecules share the
+ * GPU the way the tasks of one molecule do (Sec. III-D: independent tasks, one final reduction per
+ * output).  Packed caller layout, offsets from kldi_batch_layout: D and Vxc of molecule m are the
+ * n_ao(m) x n_ao(m) row-major blocks at d_off[m]; rho of molecule m starts at pt_off[m]; E_xc is
+ * exc[m].  Errors as kldi_plan_create; n_mol >= 1. */
+kldi_status kldi_batch_create(int32_t n_mol, const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts,
+                              void *stream, kldi_plan **out);
+
+/* Offsets of the packed layout (host arrays of n_mol + 1, any may be NULL): ao_off (first AO of each
+ * molecule in the stacked AO index; ao_off[n_mol] = total AOs), d_off (first element of D / Vxc),
+ * pt_off (first grid point). */
+kldi_status kldi_batch_layout(const kldi_plan *plan, int64_t *ao_off, int64_t *d_off, int64_t *pt_off);
+
+/* Graph mode (enable != 0): kldi_eval launches one small kernel that records its buffers and clears
+ * the counters, then replays a HIP graph captured from the plan's own launches (captured on first use,
+ * recaptured after kldi_plan_attach_mlp or kldi_plan_autotune).  Results are identical to the
+ * launch-by-launch path.  Per-stage timing is not recorded in graph mode. */
+kldi_status kldi_plan_graph(kldi_plan *plan, int32_t enable);
+
+typedef struct {
+  int32_t v_segment;                   /* chosen grid blocks per Vxc work item                      */
+  int32_t schedule;                    /* chosen kldi_schedule                                       */
+  double ms;                           /* mean ms per evaluation of the chosen configuration          */
+  int32_t n_tried;                     /* configurations timed; 0 when taken from the in-process cache */
+} kldi_tune_t;
+
+/* Autotuner: times evaluations of this plan with D_dev (device, packed as for kldi_eval) for each
+ * candidate Vxc tile depth (v_segment in {8, 16, 32, 64} whose FP64 partials fit in memory) and each
+ * kldi_schedule, reps timed evaluations each after one warm-up, keeps the fastest, and records it in
+ * an in-process cache keyed by the plan's shape (molecules, AOs, blocks, retained tiles, functional,
+ * precision) that later plans of the same shape reuse without timing.  Synchronises `stream`.
+ * Writes the choice to *out (host, may be NULL).  reps >= 1; reps = 0 only consults the cache. */
+kldi_status kldi_plan_autotune(kldi_plan *plan, const double *D_dev, int32_t reps, void *stream, kldi_tune_t *out);
+
 /* Releases the plan and its device memory (synchronises its device).  NULL is a no-op. */
 kldi_status kldi_plan_destroy(kldi_plan *plan);
 
 /* Copies the plan's sizes and structure statistics to *out (host). */
 kldi_status kldi_plan_info(const kldi_plan *plan, kldi_plan_info_t *out);
 
-/* Copies the plan's structure to caller-allocated HOST arrays (any may be NULL):
+/* Single-molecule plans only (KLDI_E_UNSUPPORTED for batches).
+ * Copies the plan's structure to caller-allocated HOST arrays (any may be NULL):
  *   ao_perm[n_ao]             internal AO index -> caller AO index
  *   pt_perm[n_points]         internal point index -> caller point index
  *   retained[n_tiles*n_blocks] 1 if (tile p, block r) is in S_Phi, at [r * n_tiles + p]
@@ -179,7 +231,7 @@ kldi_status kldi_plan_structure(const kldi_plan *plan, int32_t *ao_perm, int64_t
  * segments, symmetrisation and un-permutation.
  *   D_dev   [n_ao*n_ao] FP64, device, symmetric, caller AO order (read during the call only)
  *   rho_dev [n_points]  FP64, device, caller grid order, or NULL
- *   exc_dev [1]         FP64, device: E_xc
+ *   exc_dev [n_mol]     FP64, device: E_xc (one value per molecule of a batch)
  *   vxc_dev [n_ao*n_ao] FP64, device, symmetric, caller AO order, or NULL (then the M products are
  *                       skipped)
  * Only enqueues work on `stream`.  Errors: KLDI_E_ARG (NULL plan/D/exc), KLDI_E_HIP. */
@@ -270,7 +322,7 @@ kldi_status kldi_eval_timing(kldi_plan *plan, double *stage_ms, int32_t *n_evals
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *kldi_last_error(void);
 
-/* ABI version, currently 1. */
+/* ABI version, currently 2. */
 int32_t kldi_version(void);
 
 #ifdef __cplusplus

@@ -144,3 +144,136 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
     V[np.ix_(ao_perm, ao_perm)] = Vp
     return dict(rho=rho_c, E=E, V=V, S_phi=S_phi, S_D=S_D, b=b, s=s, a=a, z=z, nP_X=nP_X, nP_M=nP_M,
                 ao_perm=ao_perm, pt_perm=pt_perm, n_tiles=nT, n_blocks=nB)
+
+
+def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_d=1e-10, d_ao=32, G=128,
+                        rho_cut=1e-14, blocks_per_chunk=32, v_entries=None, progress=None):
+    """The same block-filtered evaluation as eval_blocked, one grid block at a time, for inputs whose
+    dense Phi does not fit in memory.
+
+    Every quantity of a grid block r (b_pr, s_pr, the executed pairs of X_pr, rho, Z_qr, z_qr and the
+    executed pairs of M at r) depends only on D and on the points of block r, so the blocks are
+    visited in order and M is accumulated over them.  Within a block, X_r = D^(r) Phi_r with D^(r)
+    the matrix D restricted to the retained tiles of r and zero on the tile pairs (p, q) outside
+    E(p, r); M += (Phi_r Z_r^T) restricted to the executed tile pairs of E_M at r.  Zero tiles add
+    exact zeros, so this is the sum over executed pairs of eq. executed_block_output.
+
+    v_entries: None (full V returned) or an [n, 2] array of caller-order (mu, nu) pairs; then only
+    those entries of V are formed (their M_{mu nu} and M_{nu mu} accumulated) and returned as "v".
+    Returns rho (caller order), E, V or v, and the executed pair counts nP_X, nP_M.
+    """
+    atom_xyz = np.asarray(atom_xyz, np.float64)
+    pts = np.asarray(pts, np.float64)
+    w = np.asarray(weights, np.float64)
+    gga = _fx.is_gga(xc)
+    ao_perm, pt_perm, _ = _reorder.orders(atom_xyz, basis, pts, point_atom)
+    nao = len(ao_perm)
+    npt = len(pt_perm)
+    Dp = np.asarray(D, np.float64)[np.ix_(ao_perm, ao_perm)]
+    T = _reorder.tiles(nao, d_ao)
+    B = _reorder.tiles(npt, G)
+    nT = len(T)
+    tile_of = np.repeat(np.arange(nT), d_ao)[:nao]          # internal AO -> its tile
+
+    a = np.zeros((nT, nT))
+    for p, (a0, a1) in enumerate(T):
+        for q, (c0, c1) in enumerate(T):
+            a[p, q] = np.max(np.abs(Dp[a0:a1, c0:c1]))
+    S_D = a >= t_b
+
+    inv_ao = np.empty(nao, np.int64)
+    inv_ao[ao_perm] = np.arange(nao)
+    if v_entries is None:
+        M = np.zeros((nao, nao))
+    else:
+        ve = np.asarray(v_entries, np.int64).reshape(-1, 2)
+        vi, vj = inv_ao[ve[:, 0]], inv_ao[ve[:, 1]]               # internal indices
+        m_ij = np.zeros(len(ve))
+        m_ji = np.zeros(len(ve))
+    rho = np.zeros(npt)
+    ef = np.zeros(npt)
+    nP_X = nP_M = 0
+    for c0b in range(0, len(B), blocks_per_chunk):
+        blocks = B[c0b:c0b + blocks_per_chunk]
+        g0c, g1c = blocks[0][0], blocks[-1][1]
+        ip = pt_perm[g0c:g1c]
+        phi_c, dphi_c = _basis.eval_ao(atom_xyz, basis, pts[ip], deriv=1)
+        phi_c = phi_c[ao_perm]
+        dphi_c = dphi_c[:, ao_perm]
+        for (g0, g1) in blocks:
+            ph = phi_c[:, g0 - g0c:g1 - g0c]
+            dph = dphi_c[:, :, g0 - g0c:g1 - g0c]
+            wr = w[pt_perm[g0:g1]]
+            # block summaries and retention at r
+            b = np.array([np.max(np.abs(ph[a0:a1])) for (a0, a1) in T])
+            if gga:
+                s = np.array([max(b[p], np.max(np.abs(dph[:, a0:a1]))) for p, (a0, a1) in enumerate(T)])
+            else:
+                s = b
+            ret = s >= t_b
+            R = np.nonzero(ret)[0]
+            if len(R) == 0:
+                continue
+            rows = np.concatenate([np.arange(*T[p]) for p in R])
+            # executable pairs of X at r: (p, q) in S_D, q retained, a_pq b_qr >= t_d
+            ex = S_D[np.ix_(R, R)] & (a[np.ix_(R, R)] * b[R][None, :] >= t_d)
+            nP_X += int(ex.sum())
+            tr = np.searchsorted(R, tile_of[rows])                # position of each row's tile in R
+            Dm = np.where(ex[np.ix_(tr, tr)], Dp[np.ix_(rows, rows)], 0.0)
+            phr = ph[rows]
+            dphr = dph[:, rows]
+            X = Dm @ phr
+            rr = np.einsum("mi,mi->i", phr, X)
+            grad = 2.0 * np.einsum("ami,mi->ai", dphr, X)
+            sig = np.einsum("ai,ai->i", grad, grad)
+            f, vr, vs = _fx.evaluate(xc, rr, sig if gga else None, rho_cut)
+            rho[g0:g1] = rr
+            ef[g0:g1] = wr * f
+            Z = 0.5 * (wr * vr)[None, :] * phr
+            if gga:
+                Z += 2.0 * (wr * vs)[None, :] * np.einsum("ai,ami->mi", grad, dphr)
+            z = np.array([np.max(np.abs(Z[tr == k])) for k in range(len(R))])
+            # executable (p, q) of M at r: both retained, z_qr >= t_b, b_pr z_qr >= t_d (LDA: p <= q)
+            exm = (z[None, :] >= t_b) & (b[R][:, None] * z[None, :] >= t_d)
+            if not gga:
+                exm &= R[:, None] <= R[None, :]
+            nP_M += int(exm.sum())
+            if v_entries is None:
+                Mr = np.where(exm[np.ix_(tr, tr)], phr @ Z.T, 0.0)
+                M[np.ix_(rows, rows)] += Mr
+            else:
+                pos = np.full(nao, -1, np.int64)
+                pos[rows] = np.arange(len(rows))
+                for (x, y, acc) in ((vi, vj, m_ij), (vj, vi, m_ji)):
+                    px, py = pos[x], pos[y]
+                    ok = (px >= 0) & (py >= 0)
+                    ok[ok] &= exm[tr[px[ok]], tr[py[ok]]]
+                    acc[ok] += np.einsum("ki,ki->k", phr[px[ok]], Z[py[ok]])
+        if progress is not None:
+            progress(c0b + len(blocks), len(B))
+    E = math.fsum(ef.tolist())
+    rho_c = np.empty(npt)
+    rho_c[pt_perm] = rho
+    out = dict(rho=rho_c, E=E, nP_X=nP_X, nP_M=nP_M, ao_perm=ao_perm, pt_perm=pt_perm)
+    if v_entries is None:
+        if gga:
+            Vp = M + M.T
+        else:
+            Vp = np.zeros_like(M)
+            for p, (a0, a1) in enumerate(T):
+                for q, (c0, c1) in enumerate(T):
+                    if q > p:
+                        Vp[a0:a1, c0:c1] = 2.0 * M[a0:a1, c0:c1]
+                        Vp[c0:c1, a0:a1] = 2.0 * M[a0:a1, c0:c1].T
+                Vp[a0:a1, a0:a1] = M[a0:a1, a0:a1] + M[a0:a1, a0:a1].T
+        V = np.empty((nao, nao))
+        V[np.ix_(ao_perm, ao_perm)] = Vp
+        out["V"] = V
+    else:
+        if gga:
+            v = m_ij + m_ji
+        else:
+            pi, pj = tile_of[vi], tile_of[vj]
+            v = np.where(pi < pj, 2.0 * m_ij, np.where(pi > pj, 2.0 * m_ji, m_ij + m_ji))
+        out["v"] = v
+    return out

@@ -23,6 +23,7 @@ STATUS = {0: "KLDI_OK", -1: "KLDI_E_ARG", -2: "KLDI_E_OOM", -3: "KLDI_E_HIP", -4
           -5: "KLDI_E_STATE", -6: "KLDI_E_NONFINITE"}
 XC = {"lda": 1, "pbe": 2, "pbe_x": 3}
 PREC = {"fp64": 0, "fp32": 1}
+SCHED = {"grid": 0, "queue": 1}
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -42,7 +43,8 @@ class kldi_grid(ctypes.Structure):
 class kldi_opts(ctypes.Structure):
     _fields_ = [("t_b", ctypes.c_double), ("t_d", ctypes.c_double), ("rho_cut", ctypes.c_double),
                 ("grid_block", ctypes.c_int32), ("ao_block", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("xc", ctypes.c_int32), ("v_segment", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32)]
+                ("xc", ctypes.c_int32), ("v_segment", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class kldi_plan_info_t(ctypes.Structure):
@@ -51,7 +53,13 @@ class kldi_plan_info_t(ctypes.Structure):
                 ("n_retained_tiles", ctypes.c_int64), ("retained_fraction", ctypes.c_double),
                 ("max_tiles_per_block", ctypes.c_int32), ("v_segment", ctypes.c_int32),
                 ("n_v_items", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("n_grid_chunks", ctypes.c_int32),
-                ("plan_ms", ctypes.c_double)]
+                ("plan_ms", ctypes.c_double), ("n_mol", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("n_x_items", ctypes.c_int64)]
+
+
+class kldi_tune_t(ctypes.Structure):
+    _fields_ = [("v_segment", ctypes.c_int32), ("schedule", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("n_tried", ctypes.c_int32)]
 
 
 class kldi_eval_stats_t(ctypes.Structure):
@@ -79,6 +87,14 @@ kldi_opts_default = _sig("kldi_opts_default", None, [ctypes.POINTER(kldi_opts)])
 kldi_plan_create = _sig("kldi_plan_create", ctypes.c_int,
                         [ctypes.POINTER(kldi_basis), ctypes.POINTER(kldi_grid), ctypes.POINTER(kldi_opts),
                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)])
+kldi_batch_create = _sig("kldi_batch_create", ctypes.c_int,
+                         [ctypes.c_int32, ctypes.POINTER(kldi_basis), ctypes.POINTER(kldi_grid), ctypes.POINTER(kldi_opts),
+                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)])
+kldi_batch_layout = _sig("kldi_batch_layout", ctypes.c_int,
+                         [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
+kldi_plan_graph = _sig("kldi_plan_graph", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32])
+kldi_plan_autotune = _sig("kldi_plan_autotune", ctypes.c_int,
+                          [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(kldi_tune_t)])
 kldi_plan_destroy = _sig("kldi_plan_destroy", ctypes.c_int, [ctypes.c_void_p])
 kldi_plan_info = _sig("kldi_plan_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(kldi_plan_info_t)])
 kldi_plan_structure = _sig("kldi_plan_structure", ctypes.c_int,
@@ -113,7 +129,8 @@ kldi_plan_attach_mlp = _sig("kldi_plan_attach_mlp", ctypes.c_int, [ctypes.c_void
 kldi_last_error = _sig("kldi_last_error", ctypes.c_char_p, [])
 kldi_version = _sig("kldi_version", ctypes.c_int32, [])
 
-EXPORTS = sorted(["kldi_opts_default", "kldi_plan_create", "kldi_plan_destroy", "kldi_plan_info",
+EXPORTS = sorted(["kldi_opts_default", "kldi_plan_create", "kldi_batch_create", "kldi_batch_layout",
+                  "kldi_plan_graph", "kldi_plan_autotune", "kldi_plan_destroy", "kldi_plan_info",
                   "kldi_plan_structure", "kldi_eval", "kldi_eval_check", "kldi_plan_timing", "kldi_eval_timing",
                   "kldi_eval_grid", "kldi_xc_eval", "kldi_mlp_create", "kldi_mlp_destroy", "kldi_mlp_train",
                   "kldi_mlp_forward", "kldi_mlp_loss_grad", "kldi_mlp_params", "kldi_plan_attach_mlp",

@@ -234,8 +234,7 @@ struct FArgs {
   const double *part;
   double *coef;                  // [n_pad][4]: w v_rho / 2, 2 w v_sigma grad rho
   double *eblk;
-  double *rho_out;
-  double *sigma_out;             // optional: sigma in caller grid order
+  const IoDev *io;               // rho / sigma outputs (caller grid order) of the running evaluation
   unsigned long long *counters;  // [3] counts points evaluated by the surrogate
   double rho_cut;
   int xc;

@@ -1,13 +1,20 @@
-// Host side of libkldi: the C ABI, argument validation and the per-geometry plan
-// (reordering, tiling, shell radii, screening, retained-block lists, work lists, workspaces).
+// Host side of libkldi: the C ABI, argument validation, the per-geometry plan (reordering, tiling,
+// shell radii, screening, retained-block lists) for one molecule or a batch of molecules, the work
+// schedule (work lists, persistent-kernel queues, workspaces), graph capture and the autotuner.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <limits>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <stdexcept>
+#include <thread>
+#include <tuple>
 
 #include "kldi_impl.h"
 
@@ -31,7 +38,7 @@ void check_hip(hipError_t e, const char *what) {
 }
 
 template <class T>
-T *dev_alloc(Plan &P, size_t n) {
+T *dev_alloc(Plan &P, size_t n, bool sched = false) {
   void *p = nullptr;
   size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
   hipError_t e = hipMalloc(&p, bytes);
@@ -39,21 +46,41 @@ T *dev_alloc(Plan &P, size_t n) {
     (void)hipGetLastError();
     fail(KLDI_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
-  P.allocs.push_back(p);
-  P.bytes += bytes;
+  if (sched) {
+    P.sched_allocs.push_back(p);
+    P.sched_bytes += bytes;
+  } else {
+    P.allocs.push_back(p);
+    P.bytes += bytes;
+  }
   return static_cast<T *>(p);
 }
 
 template <class T>
-T *dev_upload(Plan &P, const std::vector<T> &h) {
-  T *d = dev_alloc<T>(P, h.size());
+T *dev_upload(Plan &P, const std::vector<T> &h, bool sched = false) {
+  T *d = dev_alloc<T>(P, h.size(), sched);
   if (!h.empty()) check_hip(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
   return d;
 }
 
+void free_list(std::vector<void *> &v) {
+  for (void *p : v) (void)hipFree(p);
+  v.clear();
+}
+
+void free_graphs(Plan &P) {
+  for (hipGraphExec_t &g : P.graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
 void free_plan(Plan &P) {
-  for (void *p : P.allocs) (void)hipFree(p);
-  P.allocs.clear();
+  free_graphs(P);
+  if (P.cap_stream) (void)hipStreamDestroy(P.cap_stream);
+  P.cap_stream = nullptr;
+  free_list(P.sched_allocs);
+  free_list(P.allocs);
   for (hipEvent_t e : P.events) (void)hipEventDestroy(e);
   P.events.clear();
 }
@@ -135,8 +162,22 @@ bool finite_all(const double *p, int64_t n) {
   return true;
 }
 
-void validate(const kldi_basis *b, const kldi_grid *g, const kldi_opts *o) {
-  if (!b || !g || !o) fail(KLDI_E_ARG, "basis, grid and opts must not be NULL");
+void validate_opts(const kldi_opts *o) {
+  if (!(o->t_b >= 0) || !(o->t_d >= 0) || !(o->rho_cut >= 0) || !std::isfinite(o->t_b) ||
+      !std::isfinite(o->t_d) || !std::isfinite(o->rho_cut))
+    fail(KLDI_E_ARG, "t_b, t_d and rho_cut must be finite and >= 0");
+  if (o->grid_block <= 0 || o->grid_block % 64 != 0) fail(KLDI_E_ARG, "grid_block must be a positive multiple of 64");
+  if (o->grid_block != kG) fail(KLDI_E_UNSUPPORTED, "this build supports grid_block = 128");
+  if (o->ao_block != kD) fail(KLDI_E_UNSUPPORTED, "this build supports ao_block = 32");
+  if (o->prec != KLDI_PREC_FP64 && o->prec != KLDI_PREC_FP32) fail(KLDI_E_ARG, "unknown prec");
+  if (o->xc != KLDI_XC_LDA_X && o->xc != KLDI_XC_PBE && o->xc != KLDI_XC_PBE_X) fail(KLDI_E_ARG, "unknown xc");
+  if (o->v_segment < 0) fail(KLDI_E_ARG, "v_segment must be >= 0");
+  if (o->chunk_tiles < 0) fail(KLDI_E_ARG, "chunk_tiles must be >= 0");
+  if (o->schedule != KLDI_SCHED_GRID && o->schedule != KLDI_SCHED_QUEUE) fail(KLDI_E_ARG, "unknown schedule");
+}
+
+void validate(const kldi_basis *b, const kldi_grid *g) {
+  if (!b || !g) fail(KLDI_E_ARG, "basis and grid must not be NULL");
   if (b->n_atoms <= 0) fail(KLDI_E_ARG, "n_atoms must be positive");
   if (b->n_shells <= 0) fail(KLDI_E_ARG, "n_shells must be positive");
   if (!b->atom_xyz || !b->shell_atom || !b->shell_l || !b->shell_prim_ptr || !b->prim_exp || !b->prim_coef)
@@ -160,30 +201,32 @@ void validate(const kldi_basis *b, const kldi_grid *g, const kldi_opts *o) {
     fail(KLDI_E_ARG, "grid coordinates/weights not finite");
   for (int64_t i = 0; i < g->n_points; ++i)
     if (g->point_atom[i] < 0 || g->point_atom[i] >= b->n_atoms) fail(KLDI_E_ARG, "point_atom out of range");
-  if (!(o->t_b >= 0) || !(o->t_d >= 0) || !(o->rho_cut >= 0) || !std::isfinite(o->t_b) ||
-      !std::isfinite(o->t_d) || !std::isfinite(o->rho_cut))
-    fail(KLDI_E_ARG, "t_b, t_d and rho_cut must be finite and >= 0");
-  if (o->grid_block <= 0 || o->grid_block % 64 != 0) fail(KLDI_E_ARG, "grid_block must be a positive multiple of 64");
-  if (o->grid_block != kG) fail(KLDI_E_UNSUPPORTED, "this build supports grid_block = 128");
-  if (o->ao_block != kD) fail(KLDI_E_UNSUPPORTED, "this build supports ao_block = 32");
-  if (o->prec != KLDI_PREC_FP64 && o->prec != KLDI_PREC_FP32) fail(KLDI_E_ARG, "unknown prec");
-  if (o->xc != KLDI_XC_LDA_X && o->xc != KLDI_XC_PBE && o->xc != KLDI_XC_PBE_X) fail(KLDI_E_ARG, "unknown xc");
-  if (o->v_segment < 0) fail(KLDI_E_ARG, "v_segment must be >= 0");
-  if (o->chunk_tiles < 0) fail(KLDI_E_ARG, "chunk_tiles must be >= 0");
 }
 
-void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opts *o, hipStream_t stream) {
-  auto t0 = std::chrono::steady_clock::now();
-  check_hip(hipGetDevice(&P.device), "hipGetDevice");
-  P.opts = *o;
-  P.gga = (o->xc != KLDI_XC_LDA_X);
+// ------------------------------------------------------------------------------------------------
+// One molecule's reordering, tiling and candidate (tile, block) pairs, in molecule-local indices.
+// ------------------------------------------------------------------------------------------------
+struct MolPrep {
+  int n_ao = 0, n_tiles = 0, n_shells = 0;
+  int64_t n_points = 0, n_blocks = 0;
+  std::vector<int32_t> ao_perm;        // internal -> caller AO
+  std::vector<int64_t> pt_perm;        // internal -> caller point
+  std::vector<double> sh_xyz, pexp, pcoef;
+  std::vector<int> sh_prim, sh_l, sh_ao0, ao_shell, ao_comp, tile_sh, tile_nv;
+  std::vector<double> px, py, pz, pw;
+  std::vector<int64_t> porig;
+  std::vector<int> cand_p;
+  std::vector<int64_t> cand_r;
+};
+
+void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, double t_b) {
   const int na = b->n_atoms, ns = b->n_shells;
   const int64_t npt = g->n_points;
-  P.n_points = npt;
-  P.n_shells = ns;
+  M.n_points = npt;
+  M.n_shells = ns;
 
-  // ---- reordering (Sec. III-B.2): atoms by Morton key of their centres, points grouped by
-  // associated atom then Morton-sorted, AOs grouped by atom
+  // reordering (Sec. III-B.2): atoms by Morton key of their centres, points grouped by associated
+  // atom then Morton-sorted, AOs grouped by atom
   double origin[3];
   for (int d = 0; d < 3; ++d) {
     double m = b->atom_xyz[d];
@@ -209,7 +252,7 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
       off += ncart(b->shell_l[s]);
     }
     if (off > (1 << 24)) fail(KLDI_E_UNSUPPORTED, "more than 2^24 AOs");
-    P.n_ao = int(off);
+    M.n_ao = int(off);
   }
   std::vector<std::vector<int>> shells_of(na);
   for (int s = 0; s < ns; ++s) shells_of[b->shell_atom[s]].push_back(s);
@@ -217,41 +260,46 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
   for (int a : aorder)
     for (int s : shells_of[a]) shell_order.push_back(s);
 
-  P.n_tiles = (P.n_ao + kD - 1) / kD;
-  P.n_chunks = (P.n_tiles + kChunk - 1) / kChunk;
-  const int nao_pad = P.n_tiles * kD;
-  std::vector<double> sh_xyz(3 * ns), pexp, pcoef;
-  std::vector<int> sh_prim(2 * ns), sh_l(ns), sh_ao0(ns), ao_shell(nao_pad, -1), ao_comp(nao_pad, 0);
-  P.ao_perm.assign(P.n_ao, 0);
+  M.n_tiles = (M.n_ao + kD - 1) / kD;
+  const int nao_pad = M.n_tiles * kD;
+  M.sh_xyz.assign(3 * ns, 0.0);
+  M.sh_prim.assign(2 * ns, 0);
+  M.sh_l.assign(ns, 0);
+  M.sh_ao0.assign(ns, 0);
+  M.ao_shell.assign(nao_pad, -1);
+  M.ao_comp.assign(nao_pad, 0);
+  M.ao_perm.assign(M.n_ao, 0);
   {
     int ao = 0;
     for (int is = 0; is < ns; ++is) {
       int s = shell_order[is];
       int l = b->shell_l[s];
-      for (int d = 0; d < 3; ++d) sh_xyz[3 * is + d] = b->atom_xyz[3 * b->shell_atom[s] + d];
-      sh_prim[2 * is] = int(pexp.size());
+      for (int d = 0; d < 3; ++d) M.sh_xyz[3 * is + d] = b->atom_xyz[3 * b->shell_atom[s] + d];
+      M.sh_prim[2 * is] = int(M.pexp.size());
       for (int k = b->shell_prim_ptr[s]; k < b->shell_prim_ptr[s + 1]; ++k) {
-        pexp.push_back(b->prim_exp[k]);
-        pcoef.push_back(b->prim_coef[k]);
+        M.pexp.push_back(b->prim_exp[k]);
+        M.pcoef.push_back(b->prim_coef[k]);
       }
-      sh_prim[2 * is + 1] = int(pexp.size());
-      sh_l[is] = l;
-      sh_ao0[is] = ao;
+      M.sh_prim[2 * is + 1] = int(M.pexp.size());
+      M.sh_l[is] = l;
+      M.sh_ao0[is] = ao;
       for (int c = 0; c < ncart(l); ++c) {
         int lx, ly, lz;
         cart_powers(l, c, lx, ly, lz);
-        ao_shell[ao] = is;
-        ao_comp[ao] = lx | (ly << 2) | (lz << 4);
-        P.ao_perm[ao] = int32_t(cao0[s] + c);
+        M.ao_shell[ao] = is;
+        M.ao_comp[ao] = lx | (ly << 2) | (lz << 4);
+        M.ao_perm[ao] = int32_t(cao0[s] + c);
         ++ao;
       }
     }
   }
-  std::vector<int> tile_sh(2 * P.n_tiles);
-  for (int p = 0; p < P.n_tiles; ++p) {
-    int a0 = p * kD, a1 = std::min(P.n_ao, a0 + kD) - 1;
-    tile_sh[2 * p] = ao_shell[a0];
-    tile_sh[2 * p + 1] = ao_shell[a1] + 1;
+  M.tile_sh.assign(2 * M.n_tiles, 0);
+  M.tile_nv.assign(M.n_tiles, 0);
+  for (int p = 0; p < M.n_tiles; ++p) {
+    int a0 = p * kD, a1 = std::min(M.n_ao, a0 + kD) - 1;
+    M.tile_sh[2 * p] = M.ao_shell[a0];
+    M.tile_sh[2 * p + 1] = M.ao_shell[a1] + 1;
+    M.tile_nv[p] = a1 - a0 + 1;
   }
 
   // points
@@ -259,62 +307,453 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
   for (int64_t i = 0; i < npt; ++i)
     pkey[i] = morton(discretise(g->xyz[3 * i], origin[0]), discretise(g->xyz[3 * i + 1], origin[1]),
                      discretise(g->xyz[3 * i + 2], origin[2]));
-  P.pt_perm.resize(npt);
-  std::iota(P.pt_perm.begin(), P.pt_perm.end(), int64_t(0));
-  std::stable_sort(P.pt_perm.begin(), P.pt_perm.end(), [&](int64_t x, int64_t y) {
+  M.pt_perm.resize(npt);
+  std::iota(M.pt_perm.begin(), M.pt_perm.end(), int64_t(0));
+  std::stable_sort(M.pt_perm.begin(), M.pt_perm.end(), [&](int64_t x, int64_t y) {
     int rx = arank[g->point_atom[x]], ry = arank[g->point_atom[y]];
     if (rx != ry) return rx < ry;
     return pkey[x] < pkey[y];
   });
-  P.n_blocks = (npt + kG - 1) / kG;
-  P.n_pad = P.n_blocks * kG;
-  std::vector<double> px(P.n_pad), py(P.n_pad), pz(P.n_pad), pw(P.n_pad, 0.0);
-  std::vector<int64_t> porig(P.n_pad, -1);
-  for (int64_t i = 0; i < P.n_pad; ++i) {
-    int64_t c = P.pt_perm[std::min(i, npt - 1)];
-    px[i] = g->xyz[3 * c];
-    py[i] = g->xyz[3 * c + 1];
-    pz[i] = g->xyz[3 * c + 2];
+  M.n_blocks = (npt + kG - 1) / kG;
+  const int64_t n_pad = M.n_blocks * kG;
+  M.px.assign(n_pad, 0.0);
+  M.py.assign(n_pad, 0.0);
+  M.pz.assign(n_pad, 0.0);
+  M.pw.assign(n_pad, 0.0);
+  M.porig.assign(n_pad, -1);
+  for (int64_t i = 0; i < n_pad; ++i) {
+    int64_t c = M.pt_perm[std::min(i, npt - 1)];
+    M.px[i] = g->xyz[3 * c];
+    M.py[i] = g->xyz[3 * c + 1];
+    M.pz[i] = g->xyz[3 * c + 2];
     if (i < npt) {
-      pw[i] = g->weight[c];
-      porig[i] = c;
+      M.pw[i] = g->weight[c];
+      M.porig[i] = c;
     }
   }
 
-  // ---- shell radii and candidate (tile, block) pairs
+  // shell radii and candidate (tile, block) pairs: a shell of the tile within its radius of the
+  // block's bounding box
   std::vector<double> rad(ns);
   for (int is = 0; is < ns; ++is)
-    rad[is] = shell_radius(sh_l[is], &pexp[sh_prim[2 * is]], &pcoef[sh_prim[2 * is]],
-                           sh_prim[2 * is + 1] - sh_prim[2 * is], P.gga, o->t_b);
-  std::vector<int> cand_p;
-  std::vector<int64_t> cand_r;
-  for (int64_t r = 0; r < P.n_blocks; ++r) {
+    rad[is] = shell_radius(M.sh_l[is], &M.pexp[M.sh_prim[2 * is]], &M.pcoef[M.sh_prim[2 * is]],
+                           M.sh_prim[2 * is + 1] - M.sh_prim[2 * is], gga, t_b);
+  for (int64_t r = 0; r < M.n_blocks; ++r) {
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t i = r * kG; i < std::min(npt, (r + 1) * kG); ++i) {
-      lo[0] = std::min(lo[0], px[i]); hi[0] = std::max(hi[0], px[i]);
-      lo[1] = std::min(lo[1], py[i]); hi[1] = std::max(hi[1], py[i]);
-      lo[2] = std::min(lo[2], pz[i]); hi[2] = std::max(hi[2], pz[i]);
+      lo[0] = std::min(lo[0], M.px[i]); hi[0] = std::max(hi[0], M.px[i]);
+      lo[1] = std::min(lo[1], M.py[i]); hi[1] = std::max(hi[1], M.py[i]);
+      lo[2] = std::min(lo[2], M.pz[i]); hi[2] = std::max(hi[2], M.pz[i]);
     }
-    for (int p = 0; p < P.n_tiles; ++p) {
+    for (int p = 0; p < M.n_tiles; ++p) {
       bool near = false;
-      for (int is = tile_sh[2 * p]; is < tile_sh[2 * p + 1] && !near; ++is) {
+      for (int is = M.tile_sh[2 * p]; is < M.tile_sh[2 * p + 1] && !near; ++is) {
         double d2 = 0;
         for (int d = 0; d < 3; ++d) {
-          double c = sh_xyz[3 * is + d];
+          double c = M.sh_xyz[3 * is + d];
           double e = std::max(0.0, std::max(lo[d] - c, c - hi[d]));
           d2 += e * e;
         }
         near = std::sqrt(d2) <= rad[is];
       }
       if (near) {
-        cand_p.push_back(p);
-        cand_r.push_back(r);
+        M.cand_p.push_back(p);
+        M.cand_r.push_back(r);
       }
     }
   }
-  P.n_cand = int64_t(cand_p.size());
+}
 
-  // ---- device copies of basis and grid
+template <class T, class F>
+void append(std::vector<T> &dst, const std::vector<T> &src, F &&map) {
+  for (const T &v : src) dst.push_back(map(v));
+}
+
+// ------------------------------------------------------------------------------------------------
+// Work schedule: X and Vxc work lists for a Vxc segment length, grid chunks, queue orders of the
+// persistent kernels, and the workspaces sized by them.  Rebuilt by the autotuner.
+// ------------------------------------------------------------------------------------------------
+void visit_v_items(const Plan &P, const std::vector<std::vector<int>> &blk_chunks, int seg,
+                   const std::function<void(int m, int lpair, int r0, int r1)> &emit) {
+  for (int m = 0; m < P.n_mol; ++m) {
+    const MolDev &mo = P.mols_h[m];
+    const bool gga = P.gga;
+    const int nc = mo.nc;
+    std::vector<int> stamp(mo.npairs, -1);
+    auto pair_index = [&](int pc, int qc) { return gga ? pc * nc + qc : pc * nc - pc * (pc - 1) / 2 + (qc - pc); };
+    const int64_t nseg = (mo.blk1 - mo.blk0 + seg - 1) / seg;
+    for (int64_t sg = 0; sg < nseg; ++sg) {
+      const int r0 = int(mo.blk0 + sg * seg), r1 = int(std::min<int64_t>(mo.blk1, mo.blk0 + (sg + 1) * seg));
+      std::vector<int> act;
+      for (int r = r0; r < r1; ++r)
+        for (int pc : blk_chunks[r])
+          for (int qc : blk_chunks[r]) {
+            if (!gga && qc < pc) continue;
+            const int pi = pair_index(pc, qc);
+            if (stamp[pi] != int(sg)) {
+              stamp[pi] = int(sg);
+              act.push_back(pi);
+            }
+          }
+      std::sort(act.begin(), act.end());
+      for (int pi : act) emit(m, pi, r0, r1);
+    }
+  }
+}
+
+std::vector<std::vector<int>> block_chunks(const Plan &P) {
+  std::vector<std::vector<int>> bc(P.n_blocks);
+  for (int64_t r = 0; r < P.n_blocks; ++r) {
+    const int tile0 = P.mols_h[P.blk_mol_h[r]].tile0;
+    for (int64_t k = P.blk_off_h[r]; k < P.blk_off_h[r + 1]; ++k) {
+      const int c = (P.ret_p_h[k] - tile0) / kChunk;
+      if (bc[r].empty() || bc[r].back() != c) bc[r].push_back(c);
+    }
+  }
+  return bc;
+}
+
+int64_t count_v_items(const Plan &P, const std::vector<std::vector<int>> &blk_chunks, int seg) {
+  int64_t n = 0;
+  visit_v_items(P, blk_chunks, seg, [&](int, int, int, int) { ++n; });
+  return n;
+}
+
+// Split items [i0, i1) -- groups of consecutive items given by group_end -- into 8 contiguous ranges
+// of about equal cost, then order each range by decreasing group cost (items of a group stay
+// together, in their order).  Appends to order and writes 9 boundaries to qoff.
+void make_queues(int64_t i0, int64_t i1, const std::vector<int64_t> &group_start, const std::vector<double> &gcost,
+                 std::vector<int> &order, int64_t *qoff) {
+  const size_t ng = gcost.size();
+  double total = 0.0;
+  for (double c : gcost) total += c;
+  size_t g = 0;
+  double acc = 0.0;
+  for (int x = 0; x < 8; ++x) {
+    qoff[x] = int64_t(order.size());
+    const double target = total * (x + 1) / 8.0;
+    std::vector<size_t> mine;
+    while (g < ng && (acc + 0.5 * gcost[g] <= target || x == 7)) {
+      mine.push_back(g);
+      acc += gcost[g];
+      ++g;
+    }
+    std::stable_sort(mine.begin(), mine.end(), [&](size_t a, size_t b) { return gcost[a] > gcost[b]; });
+    for (size_t k : mine) {
+      const int64_t e = (k + 1 < ng) ? group_start[k + 1] : i1;
+      for (int64_t it = group_start[k]; it < e; ++it) order.push_back(int(it));
+    }
+  }
+  qoff[8] = int64_t(order.size());
+  (void)i0;
+}
+
+void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
+  free_list(P.sched_allocs);
+  P.sched_bytes = 0;
+  P.items_h.clear();
+  P.chunks_h.clear();
+  P.blk_item_off_h.clear();
+  const auto blk_chunks = block_chunks(P);
+
+  // X work items: (block, chunk of 4 consecutive retained tiles), block-major
+  std::vector<int> xr, xc;
+  std::vector<int64_t> boff(P.n_blocks + 1, 0);
+  for (int64_t r = 0; r < P.n_blocks; ++r) {
+    const int np = int(P.blk_off_h[r + 1] - P.blk_off_h[r]);
+    for (int c = 0; kChunk * c < np; ++c) {
+      xr.push_back(int(r));
+      xc.push_back(c);
+    }
+    boff[r + 1] = int64_t(xr.size());
+  }
+  P.n_xitems = int64_t(xr.size());
+  P.xit_r = dev_upload(P, xr, true);
+  P.xit_c = dev_upload(P, xc, true);
+  P.blk_item_off = dev_upload(P, boff, true);
+  P.blk_item_off_h = boff;
+
+  // Vxc work items: (molecule, row chunk, column chunk, segment of grid blocks)
+  size_t fr0 = 0, tot0 = 0;
+  check_hip(hipMemGetInfo(&fr0, &tot0), "hipMemGetInfo");
+  if (seg <= 0) {
+    // shortest segment (better L2 sharing among the items of a segment) whose FP64 partials fit a
+    // budget of min(16 GiB, 1/5 of free device memory)
+    const size_t budget = std::min<size_t>(size_t(16) << 30, fr0 / 5);
+    int64_t maxblk = 1;
+    for (const MolDev &mo : P.mols_h) maxblk = std::max<int64_t>(maxblk, mo.blk1 - mo.blk0);
+    for (seg = 16;; seg *= 2)
+      if (size_t(count_v_items(P, blk_chunks, seg)) * 16384 * 8 <= budget || seg >= maxblk) break;
+  }
+  P.v_segment = seg;
+  P.schedule = schedule;
+  std::vector<std::vector<int>> pair_lists(P.n_pairs);
+  std::vector<int> pinfo_pc(P.n_pairs), pinfo_qc(P.n_pairs);
+  for (int m = 0; m < P.n_mol; ++m) {
+    const MolDev &mo = P.mols_h[m];
+    for (int pc = 0; pc < mo.nc; ++pc)
+      for (int qc = P.gga ? 0 : pc; qc < mo.nc; ++qc) {
+        const int lp = P.gga ? pc * mo.nc + qc : pc * mo.nc - pc * (pc - 1) / 2 + (qc - pc);
+        pinfo_pc[mo.pair0 + lp] = pc;
+        pinfo_qc[mo.pair0 + lp] = qc;
+      }
+  }
+  visit_v_items(P, blk_chunks, seg, [&](int m, int lp, int r0, int r1) {
+    const int gp = P.mols_h[m].pair0 + lp;
+    pair_lists[gp].push_back(int(P.items_h.size()));
+    VItem it;
+    it.pc = pinfo_pc[gp];
+    it.qc = pinfo_qc[gp];
+    it.r0 = r0;
+    it.r1 = r1;
+    it.pair = gp;
+    it.lpair = lp;
+    P.items_h.push_back(it);
+  });
+  std::vector<int> pair_ptr(P.n_pairs + 1, 0), pair_items;
+  for (int i = 0; i < P.n_pairs; ++i) {
+    pair_ptr[i + 1] = pair_ptr[i] + int(pair_lists[i].size());
+    pair_items.insert(pair_items.end(), pair_lists[i].begin(), pair_lists[i].end());
+  }
+  P.items = dev_upload(P, P.items_h, true);
+  P.pair_ptr = dev_upload(P, pair_ptr, true);
+  P.pair_items = dev_upload(P, pair_items, true);
+
+  // all segments of all molecules in block order (they partition the blocks) and their item ranges
+  // (items are emitted segment by segment)
+  std::vector<int64_t> seg_r0, seg_r1, seg_it0, seg_it1;
+  {
+    size_t it = 0;
+    for (const MolDev &mo : P.mols_h)
+      for (int64_t r0 = mo.blk0; r0 < mo.blk1; r0 += seg) {
+        const int64_t r1 = std::min<int64_t>(mo.blk1, r0 + seg);
+        seg_r0.push_back(r0);
+        seg_r1.push_back(r1);
+        seg_it0.push_back(int64_t(it));
+        while (it < P.items_h.size() && P.items_h[it].r0 == r0) ++it;
+        seg_it1.push_back(int64_t(it));
+      }
+    if (it != P.items_h.size()) fail(KLDI_E_ARG, "internal: Vxc items out of segment order");
+  }
+  const int64_t n_segs = int64_t(seg_r0.size());
+
+  // grid chunks: whole segments whose retained tiles fit the Phi / Z workspaces
+  const size_t esz = (P.opts.prec == KLDI_PREC_FP64) ? 8 : 4;
+  const size_t per_tile = 2 * 4096 * esz;       // Phi + Z
+  const size_t vfixed = P.items_h.size() * (16384 * 8 + 4);
+  int64_t cap = chunk_tiles;
+  {
+    const size_t reserve = size_t(1) << 30;
+    if (vfixed + reserve > fr0) fail(KLDI_E_OOM, "Vxc partials need " + std::to_string(vfixed >> 20) + " MiB");
+    const int64_t fit = int64_t((fr0 - vfixed - reserve) * 0.8 / (per_tile + 4096));
+    if (cap <= 0 || cap > fit) cap = fit;
+    if (cap < 1) fail(KLDI_E_OOM, "no room for the Phi / Z workspaces");
+  }
+  for (int64_t s0 = 0; s0 < n_segs;) {
+    int64_t s1 = s0 + 1;
+    while (s1 < n_segs && P.blk_off_h[seg_r1[s1]] - P.blk_off_h[seg_r0[s0]] <= cap) ++s1;
+    GridChunk C;
+    C.blk0 = seg_r0[s0];
+    C.blk1 = seg_r1[s1 - 1];
+    C.ret0 = P.blk_off_h[C.blk0];
+    C.ret1 = P.blk_off_h[C.blk1];
+    C.xit0 = P.blk_item_off_h[C.blk0];
+    C.xit1 = P.blk_item_off_h[C.blk1];
+    C.vit0 = seg_it0[s0];
+    C.vit1 = seg_it1[s1 - 1];
+    P.chunks_h.push_back(C);
+    s0 = s1;
+  }
+  int64_t max_ret = 1, max_xit = 1, max_vm = 1;
+  for (const GridChunk &C : P.chunks_h) {
+    max_ret = std::max(max_ret, C.ret1 - C.ret0);
+    max_xit = std::max(max_xit, C.xit1 - C.xit0);
+    max_vm = std::max(max_vm, P.vmoff_h[C.blk1] - P.vmoff_h[C.blk0]);
+  }
+
+  // queues of the persistent schedule, per grid chunk
+  const size_t nch = P.chunks_h.size();
+  {
+    std::vector<int> xorder, vorder;
+    std::vector<int64_t> xqoff(9 * nch), vqoff(9 * nch);
+    for (size_t ci = 0; ci < nch; ++ci) {
+      const GridChunk &C = P.chunks_h[ci];
+      // X: groups = blocks, cost ~ retained tiles of the block (the K extent) per item
+      std::vector<int64_t> gs;
+      std::vector<double> gc;
+      for (int64_t r = C.blk0; r < C.blk1; ++r) {
+        if (P.blk_item_off_h[r + 1] == P.blk_item_off_h[r]) continue;
+        gs.push_back(P.blk_item_off_h[r]);
+        const double np = double(P.blk_off_h[r + 1] - P.blk_off_h[r]);
+        gc.push_back(double(P.blk_item_off_h[r + 1] - P.blk_item_off_h[r]) * (np + 4.0));
+      }
+      make_queues(C.xit0, C.xit1, gs, gc, xorder, &xqoff[9 * ci]);
+      // V: one group per item, cost ~ candidate tile pairs over its segment
+      std::vector<int64_t> vs;
+      std::vector<double> vc;
+      for (int64_t it = C.vit0; it < C.vit1; ++it) {
+        const VItem &v = P.items_h[it];
+        double c = 1.0;
+        for (int r = v.r0; r < v.r1; ++r) {
+          const int *ci_r = P.cinfo_h.data() + P.cioff_h[r];
+          c += double(__builtin_popcount(ci_r[v.pc] & 15) * __builtin_popcount(ci_r[v.qc] & 15));
+        }
+        vs.push_back(it);
+        vc.push_back(c);
+      }
+      make_queues(C.vit0, C.vit1, vs, vc, vorder, &vqoff[9 * ci]);
+    }
+    P.xq.order = dev_upload(P, xorder, true);
+    P.xq.qoff = dev_upload(P, xqoff, true);
+    P.vq.order = dev_upload(P, vorder, true);
+    P.vq.qoff = dev_upload(P, vqoff, true);
+  }
+
+  EvalDev &E = P.ev;
+  if (esz == 8) {
+    E.phi = dev_alloc<double>(P, size_t(max_ret) * 4096, true);
+    E.zws = dev_alloc<double>(P, size_t(max_ret) * 4096, true);
+  } else {
+    E.phi = dev_alloc<float>(P, size_t(max_ret) * 4096, true);
+    E.zws = dev_alloc<float>(P, size_t(max_ret) * 4096, true);
+  }
+  E.xpart = dev_alloc<double>(P, size_t(max_xit) * 4 * kG, true);
+  E.vpart = dev_alloc<double>(P, P.items_h.size() * 16384, true);
+  E.vflag = dev_alloc<int>(P, P.items_h.size(), true);
+  E.vmask = dev_alloc<unsigned short>(P, size_t(max_vm), true);
+  E.qcnt = dev_alloc<int>(P, 16 * nch, true);
+}
+
+// ------------------------------------------------------------------------------------------------
+// The plan over n_mol molecules
+// ------------------------------------------------------------------------------------------------
+void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, const kldi_opts *o,
+                hipStream_t stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  check_hip(hipGetDevice(&P.device), "hipGetDevice");
+  check_hip(hipDeviceGetAttribute(&P.n_cu, hipDeviceAttributeMultiprocessorCount, P.device), "device attribute");
+  P.opts = *o;
+  P.gga = (o->xc != KLDI_XC_LDA_X);
+  P.n_mol = n_mol;
+
+  // per-molecule preparation on host threads
+  std::vector<MolPrep> mp(n_mol);
+  {
+    std::atomic<int> next{0};
+    std::vector<std::string> errs(n_mol);
+    std::vector<kldi_status> codes(n_mol, KLDI_OK);
+    const int nth = std::max(1, std::min<int>(n_mol, int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())))));
+    auto work = [&] {
+      for (int m = next++; m < n_mol; m = next++) {
+        try {
+          prepare_mol(mp[m], &bs[m], &gs[m], P.gga, o->t_b);
+        } catch (const Error &e) {
+          codes[m] = e.code;
+          errs[m] = e.msg;
+        } catch (const std::bad_alloc &) {
+          codes[m] = KLDI_E_OOM;
+          errs[m] = "host allocation failed";
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; ++t) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+    for (int m = 0; m < n_mol; ++m)
+      if (codes[m] != KLDI_OK) fail(codes[m], "molecule " + std::to_string(m) + ": " + errs[m]);
+  }
+
+  // one index space: offsets of every molecule
+  std::vector<int> shell0(n_mol), prim0(n_mol);
+  P.mols_h.resize(n_mol);
+  int ns = 0, npr = 0, nt = 0, npairs = 0;
+  int64_t nblk = 0, row = 0, dt = 0, d0 = 0, mf = 0, pt0 = 0;
+  for (int m = 0; m < n_mol; ++m) {
+    const MolPrep &M = mp[m];
+    MolDev &mo = P.mols_h[m];
+    shell0[m] = ns;
+    prim0[m] = npr;
+    mo.tile0 = nt;
+    mo.nt = M.n_tiles;
+    mo.nc = (M.n_tiles + kChunk - 1) / kChunk;
+    mo.pair0 = npairs;
+    mo.npairs = P.gga ? mo.nc * mo.nc : mo.nc * (mo.nc + 1) / 2;
+    mo.n_ao = M.n_ao;
+    mo.ld = mo.nc * 128;
+    mo.pad_ = 0;
+    mo.row0 = row;
+    mo.dt0 = dt;
+    mo.d0 = d0;
+    mo.blk0 = nblk;
+    mo.blk1 = nblk + M.n_blocks;
+    mo.mf0 = mf;
+    ns += M.n_shells;
+    npr += int(M.pexp.size());
+    nt += M.n_tiles;
+    npairs += mo.npairs;
+    nblk += M.n_blocks;
+    row += M.n_ao;
+    dt += int64_t(M.n_tiles) * M.n_tiles;
+    d0 += int64_t(M.n_ao) * M.n_ao;
+    mf += int64_t(mo.ld) * mo.ld;
+    pt0 += M.n_points;
+    P.max_nao = std::max(P.max_nao, M.n_ao);
+  }
+  if (int64_t(nt) * kD > (int64_t(1) << 30)) fail(KLDI_E_UNSUPPORTED, "too many AOs in one plan");
+  P.n_shells = ns;
+  P.n_tiles = nt;
+  P.n_ao = int(row);
+  P.n_pairs = npairs;
+  P.n_blocks = nblk;
+  P.n_pad = nblk * kG;
+  P.n_points = pt0;
+  P.n_dt = dt;
+  P.n_mfull = mf;
+  if (n_mol == 1) P.pt_perm = mp[0].pt_perm;
+  P.pt_off_h.assign(n_mol + 1, 0);
+  for (int m = 0; m < n_mol; ++m) P.pt_off_h[m + 1] = P.pt_off_h[m] + mp[m].n_points;
+
+  // concatenated host arrays
+  std::vector<double> sh_xyz, pexp, pcoef, px, py, pz, pw;
+  std::vector<int> sh_prim, sh_l, sh_ao0, ao_shell, ao_comp, tile_sh, tile_nv, cand_p;
+  std::vector<int64_t> porig, cand_r;
+  std::vector<int32_t> blk_mol(nblk);
+  P.ao_perm.assign(size_t(nt) * kD, 0);
+  {
+    int64_t ptoff = 0;
+    for (int m = 0; m < n_mol; ++m) {
+      const MolPrep &M = mp[m];
+      const MolDev &mo = P.mols_h[m];
+      const int s0 = shell0[m], q0 = prim0[m], a0 = mo.tile0 * kD;
+      append(sh_xyz, M.sh_xyz, [](double v) { return v; });
+      for (size_t k = 0; k < M.sh_prim.size(); ++k) sh_prim.push_back(M.sh_prim[k] + q0);
+      append(sh_l, M.sh_l, [](int v) { return v; });
+      append(sh_ao0, M.sh_ao0, [&](int v) { return v + a0; });
+      append(pexp, M.pexp, [](double v) { return v; });
+      append(pcoef, M.pcoef, [](double v) { return v; });
+      append(ao_shell, M.ao_shell, [&](int v) { return v < 0 ? -1 : v + s0; });
+      append(ao_comp, M.ao_comp, [](int v) { return v; });
+      append(tile_sh, M.tile_sh, [&](int v) { return v + s0; });
+      append(tile_nv, M.tile_nv, [](int v) { return v; });
+      append(px, M.px, [](double v) { return v; });
+      append(py, M.py, [](double v) { return v; });
+      append(pz, M.pz, [](double v) { return v; });
+      append(pw, M.pw, [](double v) { return v; });
+      append(porig, M.porig, [&](int64_t v) { return v < 0 ? int64_t(-1) : v + ptoff; });
+      append(cand_p, M.cand_p, [&](int v) { return v + mo.tile0; });
+      append(cand_r, M.cand_r, [&](int64_t v) { return v + mo.blk0; });
+      for (int i = 0; i < M.n_ao; ++i) P.ao_perm[size_t(a0) + i] = M.ao_perm[i];
+      for (int64_t r = mo.blk0; r < mo.blk1; ++r) blk_mol[r] = m;
+      ptoff += M.n_points;
+    }
+  }
+  mp.clear();
+  mp.shrink_to_fit();
+  P.n_cand = int64_t(cand_p.size());
+  P.blk_mol_h = blk_mol;
+
+  // device copies of basis, grid and molecule table
   BasisDev &B = P.basis;
   B.sh_xyz = dev_upload(P, sh_xyz);
   B.sh_prim = dev_upload(P, sh_prim);
@@ -325,8 +764,7 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
   B.ao_shell = dev_upload(P, ao_shell);
   B.ao_comp = dev_upload(P, ao_comp);
   B.tile_sh = dev_upload(P, tile_sh);
-  B.n_ao = P.n_ao;
-  B.n_tiles = P.n_tiles;
+  B.tile_nv = dev_upload(P, tile_nv);
   GridDev &Gd = P.grid;
   Gd.x = dev_upload(P, px);
   Gd.y = dev_upload(P, py);
@@ -334,8 +772,9 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
   Gd.w = dev_upload(P, pw);
   Gd.orig = dev_upload(P, porig);
   Gd.n_blocks = P.n_blocks;
+  px = py = pz = pw = std::vector<double>();
 
-  // ---- exact block maxima on the device (eq. block_summary_A), retention (eq. block_filter_A)
+  // exact block maxima on the device (eq. block_summary_A), retention (eq. block_filter_A)
   std::vector<double> cb(P.n_cand), cg(P.n_cand);
   if (P.n_cand > 0) {
     int *dcp = dev_upload(P, cand_p);
@@ -356,12 +795,10 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
   }
   P.blk_off_h.assign(P.n_blocks + 1, 0);
   std::vector<int> ret_r;
-  std::vector<int> idx_map(size_t(P.n_blocks) * P.n_tiles, -1);
   for (int64_t c = 0; c < P.n_cand; ++c) {
     double s = P.gga ? std::max(cb[c], cg[c]) : cb[c];
     if (s >= o->t_b) {
       int64_t r = cand_r[c];
-      idx_map[size_t(r) * P.n_tiles + cand_p[c]] = int(P.blk_off_h[r + 1]);
       P.blk_off_h[r + 1]++;
       P.ret_p_h.push_back(cand_p[c]);
       ret_r.push_back(int(r));
@@ -378,181 +815,109 @@ void build_plan(Plan &P, const kldi_basis *b, const kldi_grid *g, const kldi_opt
   S.blk_off = dev_upload(P, P.blk_off_h);
   S.ret_p = dev_upload(P, P.ret_p_h);
   S.ret_r = dev_upload(P, ret_r);
-  S.idx_map = dev_upload(P, idx_map);
   S.bphi = dev_upload(P, P.bphi_h);
-  // X work items: (block, chunk of 4 consecutive retained tiles), block-major
-  {
-    std::vector<int> xr, xc;
-    std::vector<int64_t> boff(P.n_blocks + 1, 0);
-    for (int64_t r = 0; r < P.n_blocks; ++r) {
-      const int np = int(P.blk_off_h[r + 1] - P.blk_off_h[r]);
-      for (int c = 0; kChunk * c < np; ++c) {
-        xr.push_back(int(r));
-        xc.push_back(c);
-      }
-      boff[r + 1] = int64_t(xr.size());
-    }
-    P.n_xitems = int64_t(xr.size());
-    P.xit_r = dev_upload(P, xr);
-    P.xit_c = dev_upload(P, xc);
-    P.blk_item_off = dev_upload(P, boff);
-    P.blk_item_off_h = boff;
-  }
+  S.blk_mol = dev_upload(P, blk_mol);
+  S.mol = dev_upload(P, P.mols_h);
+  S.n_mol = n_mol;
 
-  // ---- Vxc work list: (row chunk, column chunk, segment of grid blocks)
-  const int nc = P.n_chunks;
-  const int npairs = P.gga ? nc * nc : nc * (nc + 1) / 2;
-  P.n_pairs = npairs;
-  auto pair_index = [&](int pc, int qc) { return P.gga ? pc * nc + qc : pc * nc - pc * (pc - 1) / 2 + (qc - pc); };
-  // chunks present at each block
-  std::vector<std::vector<int>> blk_chunks(P.n_blocks);
-  for (int64_t r = 0; r < P.n_blocks; ++r)
-    for (int64_t k = P.blk_off_h[r]; k < P.blk_off_h[r + 1]; ++k) {
-      const int c = P.ret_p_h[k] / kChunk;
-      if (blk_chunks[r].empty() || blk_chunks[r].back() != c) blk_chunks[r].push_back(c);
-    }
-  // work items of a segment length: the chunk pairs that co-occur at some block of the segment
-  std::vector<int> stamp(npairs, -1);
-  auto visit_items = [&](int seg, auto &&emit) {
-    const int64_t nseg = (P.n_blocks + seg - 1) / seg;
-    for (int64_t sg = 0; sg < nseg; ++sg) {
-      const int r0 = int(sg * seg), r1 = int(std::min<int64_t>(P.n_blocks, (sg + 1) * seg));
-      std::vector<int> act;
-      for (int r = r0; r < r1; ++r)
-        for (int pc : blk_chunks[r])
-          for (int qc : blk_chunks[r]) {
-            if (!P.gga && qc < pc) continue;
-            const int pi = pair_index(pc, qc);
-            if (stamp[pi] != int(sg)) {
-              stamp[pi] = int(sg);
-              act.push_back(pi);
-            }
-          }
-      std::sort(act.begin(), act.end());
-      for (int pi : act) emit(pi, r0, r1);
-    }
-    std::fill(stamp.begin(), stamp.end(), -1);
-  };
-  int seg = o->v_segment;
-  if (seg <= 0) {
-    // shortest segment (better L2 sharing among the items of a segment) whose FP64 partials fit a
-    // budget of min(16 GiB, 1/5 of free device memory)
-    size_t fr0 = 0, tot0 = 0;
-    check_hip(hipMemGetInfo(&fr0, &tot0), "hipMemGetInfo");
-    const size_t budget = std::min<size_t>(size_t(16) << 30, fr0 / 5);
-    for (seg = 16;; seg *= 2) {
-      int64_t n = 0;
-      visit_items(seg, [&](int, int, int) { ++n; });
-      if (size_t(n) * 16384 * 8 <= budget || seg >= P.n_blocks) break;
+  // per (block, chunk of its molecule): position in S_r of the chunk's first retained tile and its
+  // 4-bit mask; per block: first cinfo entry and first Vxc-mask entry; the chunk-pair table
+  P.cioff_h.assign(P.n_blocks + 1, 0);
+  P.vmoff_h.assign(P.n_blocks + 1, 0);
+  for (int64_t r = 0; r < P.n_blocks; ++r) {
+    const MolDev &mo = P.mols_h[blk_mol[r]];
+    P.cioff_h[r + 1] = P.cioff_h[r] + mo.nc;
+    P.vmoff_h[r + 1] = P.vmoff_h[r] + mo.npairs;
+  }
+  P.cinfo_h.assign(size_t(P.cioff_h[P.n_blocks]), 0);
+  for (int64_t r = 0; r < P.n_blocks; ++r) {
+    const int tile0 = P.mols_h[blk_mol[r]].tile0;
+    for (int64_t k = P.blk_off_h[r + 1] - 1; k >= P.blk_off_h[r]; --k) {
+      const int p = P.ret_p_h[k] - tile0, c = p / kChunk;
+      int &ci = P.cinfo_h[size_t(P.cioff_h[r]) + c];
+      ci = (int(k - P.blk_off_h[r]) << 4) | (ci & 15) | (1 << (p % kChunk));
     }
   }
-  P.v_segment = seg;
-  std::vector<std::vector<int>> pair_lists(npairs);
-  std::vector<int> pair_pc(npairs), pair_qc(npairs);
-  for (int pc = 0; pc < nc; ++pc)
-    for (int qc = P.gga ? 0 : pc; qc < nc; ++qc) {
-      pair_pc[pair_index(pc, qc)] = pc;
-      pair_qc[pair_index(pc, qc)] = qc;
-    }
-  const int64_t n_segs = (P.n_blocks + seg - 1) / seg;
-  std::vector<int64_t> seg_item_off(n_segs + 1, 0);
-  visit_items(seg, [&](int pi, int r0, int r1) {
-    pair_lists[pi].push_back(int(P.items_h.size()));
-    P.items_h.push_back(VItem{pair_pc[pi], pair_qc[pi], r0, r1, pi, 0});
-    seg_item_off[r0 / seg + 1] = int64_t(P.items_h.size());
-  });
-  for (int64_t sg = 1; sg <= n_segs; ++sg) seg_item_off[sg] = std::max(seg_item_off[sg], seg_item_off[sg - 1]);
-  std::vector<int> pair_ptr(npairs + 1, 0), pair_items, pair_pq(2 * npairs);
-  for (int i = 0; i < npairs; ++i) {
-    pair_pq[2 * i] = pair_pc[i];
-    pair_pq[2 * i + 1] = pair_qc[i];
-  }
-  for (int i = 0; i < npairs; ++i) {
-    pair_ptr[i + 1] = pair_ptr[i] + int(pair_lists[i].size());
-    pair_items.insert(pair_items.end(), pair_lists[i].begin(), pair_lists[i].end());
-  }
-  P.items = dev_upload(P, P.items_h);
-  P.pair_ptr = dev_upload(P, pair_ptr);
-  P.pair_items = dev_upload(P, pair_items);
-  P.pair_pq = dev_upload(P, pair_pq);
+  P.cinfo = dev_upload(P, P.cinfo_h);
+  P.cioff = dev_upload(P, P.cioff_h);
+  P.vmoff = dev_upload(P, P.vmoff_h);
   {
-    // per (block, chunk): position in S_r of the chunk's first retained tile, and its 4-bit mask
-    std::vector<int> cinfo(size_t(P.n_blocks) * nc, 0);
-    for (int64_t r = 0; r < P.n_blocks; ++r)
-      for (int64_t k = P.blk_off_h[r + 1] - 1; k >= P.blk_off_h[r]; --k) {
-        const int p = P.ret_p_h[k], c = p / kChunk;
-        int &ci = cinfo[size_t(r) * nc + c];
-        ci = (int(k - P.blk_off_h[r]) << 4) | (ci & 15) | (1 << (p % kChunk));
-      }
-    P.cinfo = dev_upload(P, cinfo);
+    std::vector<int> pinfo(3 * size_t(P.n_pairs));
+    for (int m = 0; m < n_mol; ++m) {
+      const MolDev &mo = P.mols_h[m];
+      for (int pc = 0; pc < mo.nc; ++pc)
+        for (int qc = P.gga ? 0 : pc; qc < mo.nc; ++qc) {
+          const int lp = P.gga ? pc * mo.nc + qc : pc * mo.nc - pc * (pc - 1) / 2 + (qc - pc);
+          const size_t g = size_t(mo.pair0 + lp);
+          pinfo[3 * g] = pc;
+          pinfo[3 * g + 1] = qc;
+          pinfo[3 * g + 2] = m;
+        }
+    }
+    P.pair_info = dev_upload(P, pinfo);
   }
   P.ao_perm_d = dev_upload(P, P.ao_perm);
 
-  // ---- grid chunks: whole Vxc segments whose retained tiles fit the Phi / Z workspaces
+  // fixed workspaces
   const size_t esz = (o->prec == KLDI_PREC_FP64) ? 8 : 4;
-  const size_t fixed = size_t(P.items_h.size()) * 16384 * 8 + size_t(nc * kChunk * kD) * size_t(nc * kChunk * kD) * 8 +
-                       size_t(P.n_pad) * 32 + size_t(P.n_ret) * 8 + size_t(P.n_tiles) * P.n_tiles * (1024 * esz + 8);
-  const size_t per_tile = 2 * 4096 * esz;       // Phi + Z
-  int64_t cap = o->chunk_tiles;
-  {
-    size_t fr = 0, tot = 0;
-    check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
-    const size_t reserve = size_t(1) << 30;
-    if (fixed + reserve > fr) fail(KLDI_E_OOM, "fixed workspaces need " + std::to_string(fixed >> 20) + " MiB");
-    const int64_t fit = int64_t((fr - fixed - reserve) * 0.8 / (per_tile + 4096));
-    if (cap <= 0 || cap > fit) cap = fit;
-  }
-  {
-    int64_t s0 = 0;
-    while (s0 < n_segs) {
-      int64_t s1 = s0 + 1;
-      auto ret_of = [&](int64_t a, int64_t b) {
-        return P.blk_off_h[std::min<int64_t>(P.n_blocks, b * seg)] - P.blk_off_h[a * seg];
-      };
-      while (s1 < n_segs && ret_of(s0, s1 + 1) <= cap) ++s1;
-      GridChunk C;
-      C.blk0 = s0 * seg;
-      C.blk1 = std::min<int64_t>(P.n_blocks, s1 * seg);
-      C.ret0 = P.blk_off_h[C.blk0];
-      C.ret1 = P.blk_off_h[C.blk1];
-      C.xit0 = P.blk_item_off_h[C.blk0];
-      C.xit1 = P.blk_item_off_h[C.blk1];
-      C.vit0 = seg_item_off[s0];
-      C.vit1 = seg_item_off[s1];
-      P.chunks_h.push_back(C);
-      s0 = s1;
-    }
-  }
-  int64_t max_ret = 0, max_xit = 0, max_blk = 0;
-  for (const GridChunk &C : P.chunks_h) {
-    max_ret = std::max(max_ret, C.ret1 - C.ret0);
-    max_xit = std::max(max_xit, C.xit1 - C.xit0);
-    max_blk = std::max(max_blk, C.blk1 - C.blk0);
-  }
   EvalDev &E = P.ev;
-  size_t nt2 = size_t(P.n_tiles) * P.n_tiles;
-  E.Dt = (esz == 8) ? (void *)dev_alloc<double>(P, nt2 * 1024) : (void *)dev_alloc<float>(P, nt2 * 1024);
-  E.amax = dev_alloc<double>(P, nt2);
-  if (esz == 8) {
-    E.phi = dev_alloc<double>(P, size_t(max_ret) * 4096);
-    E.zws = dev_alloc<double>(P, size_t(max_ret) * 4096);
-  } else {
-    E.phi = dev_alloc<float>(P, size_t(max_ret) * 4096);
-    E.zws = dev_alloc<float>(P, size_t(max_ret) * 4096);
-  }
+  E.Dt = (esz == 8) ? (void *)dev_alloc<double>(P, size_t(P.n_dt) * 1024) : (void *)dev_alloc<float>(P, size_t(P.n_dt) * 1024);
+  E.amax = dev_alloc<double>(P, size_t(P.n_dt));
   E.zmax = dev_alloc<double>(P, P.n_ret);
-  E.xpart = dev_alloc<double>(P, size_t(max_xit) * 4 * kG);
   E.coef = dev_alloc<double>(P, size_t(P.n_pad) * 4);
   E.eblk = dev_alloc<double>(P, P.n_blocks);
-  E.vpart = dev_alloc<double>(P, P.items_h.size() * 16384);
-  E.vflag = dev_alloc<int>(P, P.items_h.size());
-  E.vmask = dev_alloc<unsigned short>(P, size_t(max_blk) * npairs);
-  E.mfull = dev_alloc<double>(P, size_t(nc * kChunk * kD) * size_t(nc * kChunk * kD));
+  E.mfull = dev_alloc<double>(P, size_t(P.n_mfull));
   E.counters = dev_alloc<unsigned long long>(P, 4);
-  E.escratch = dev_alloc<double>(P, 1);
+  E.escratch = dev_alloc<double>(P, n_mol);
+  E.io = dev_alloc<IoDev>(P, 1);
   check_hip(hipMemsetAsync(E.counters, 0, 4 * sizeof(unsigned long long), stream), "memset");
   check_hip(hipStreamSynchronize(stream), "plan sync");
+
+  build_schedule(P, o->v_segment, o->schedule, o->chunk_tiles);
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ------------------------------------------------------------------------------------------------
+// One evaluation: k_begin, then the body launch by launch or as a captured graph
+// ------------------------------------------------------------------------------------------------
+void run_eval(Plan &P, const IoDev &io, bool want_v, hipStream_t s, hipEvent_t *ev) {
+  check_hip(launch_begin(P, io, s), "begin launch");
+  if (!P.use_graph) {
+    check_hip(launch_body(P, want_v, s, ev), "eval launch");
+    return;
+  }
+  hipGraphExec_t &gx = P.graph[want_v ? 1 : 0];
+  if (!gx) {
+    if (!P.cap_stream) check_hip(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    hipGraph_t g = nullptr;
+    check_hip(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    const hipError_t le = launch_body(P, want_v, P.cap_stream, nullptr);
+    const hipError_t ce = hipStreamEndCapture(P.cap_stream, &g);
+    check_hip(le, "launch during capture");
+    check_hip(ce, "hipStreamEndCapture");
+    const hipError_t ie = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    check_hip(ie, "hipGraphInstantiate");
+  }
+  check_hip(hipGraphLaunch(gx, s), "hipGraphLaunch");
+}
+
+hipEvent_t *timing_slot(Plan &P) {
+  if (!P.timing || P.use_graph) return nullptr;
+  hipEvent_t *ev = &P.events[size_t(P.n_timed % kTimingSlots) * (KLDI_N_STAGES + 1)];
+  P.n_timed++;
+  return ev;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Autotuner cache: plan shape -> (v_segment, schedule)
+// ------------------------------------------------------------------------------------------------
+typedef std::tuple<int, int64_t, int64_t, int64_t, int, int> TuneKey;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+
+TuneKey tune_key(const Plan &P) {
+  return TuneKey(P.n_mol, int64_t(P.n_ao), P.n_blocks, P.n_ret, P.opts.xc, P.opts.prec);
 }
 
 template <class F>
@@ -575,7 +940,44 @@ kldi_status guarded(F &&f) {
   }
 }
 
+kldi_status create(int32_t n_mol, const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts,
+                   void *stream, kldi_plan **out) {
+  set_error("");
+  if (!out) {
+    set_error("out must not be NULL");
+    return KLDI_E_ARG;
+  }
+  *out = nullptr;
+  kldi_plan *plan = nullptr;
+  kldi_status st = guarded([&] {
+    if (n_mol < 1) fail(KLDI_E_ARG, "n_mol must be >= 1");
+    if (!basis || !grid || !opts) fail(KLDI_E_ARG, "basis, grid and opts must not be NULL");
+    validate_opts(opts);
+    for (int m = 0; m < n_mol; ++m) {
+      try {
+        validate(&basis[m], &grid[m]);
+      } catch (const Error &e) {
+        fail(e.code, n_mol > 1 ? "molecule " + std::to_string(m) + ": " + e.msg : e.msg);
+      }
+    }
+    plan = new kldi_plan();
+    build_plan(plan->impl, n_mol, basis, grid, opts, static_cast<hipStream_t>(stream));
+  });
+  if (st != KLDI_OK) {
+    if (plan) {
+      free_plan(plan->impl);
+      delete plan;
+    }
+    return st;
+  }
+  *out = plan;
+  return KLDI_OK;
+}
+
 }  // namespace
+
+void invalidate_graphs(Plan &P) { free_graphs(P); }
+
 }  // namespace kldi
 
 using kldi::Plan;
@@ -593,30 +995,34 @@ void kldi_opts_default(kldi_opts *o) {
   o->prec = KLDI_PREC_FP64;
   o->xc = KLDI_XC_LDA_X;
   o->v_segment = 0;
+  o->chunk_tiles = 0;
+  o->schedule = KLDI_SCHED_GRID;
 }
 
 kldi_status kldi_plan_create(const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts, void *stream,
                              kldi_plan **out) {
-  kldi::set_error("");
-  if (!out) {
-    kldi::set_error("out must not be NULL");
+  return kldi::create(1, basis, grid, opts, stream, out);
+}
+
+kldi_status kldi_batch_create(int32_t n_mol, const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts,
+                              void *stream, kldi_plan **out) {
+  return kldi::create(n_mol, basis, grid, opts, stream, out);
+}
+
+kldi_status kldi_batch_layout(const kldi_plan *plan, int64_t *ao_off, int64_t *d_off, int64_t *pt_off) {
+  if (!plan) {
+    kldi::set_error("plan must not be NULL");
     return KLDI_E_ARG;
   }
-  *out = nullptr;
-  kldi_plan *plan = nullptr;
-  kldi_status st = kldi::guarded([&] {
-    kldi::validate(basis, grid, opts);
-    plan = new kldi_plan();
-    kldi::build_plan(plan->impl, basis, grid, opts, static_cast<hipStream_t>(stream));
-  });
-  if (st != KLDI_OK) {
-    if (plan) {
-      kldi::free_plan(plan->impl);
-      delete plan;
+  const Plan &P = plan->impl;
+  for (int m = 0; m <= P.n_mol; ++m) {
+    if (ao_off) ao_off[m] = (m < P.n_mol) ? P.mols_h[m].row0 : int64_t(P.n_ao);
+    if (d_off) {
+      const kldi::MolDev &last = P.mols_h.back();
+      d_off[m] = (m < P.n_mol) ? P.mols_h[m].d0 : last.d0 + int64_t(last.n_ao) * last.n_ao;
     }
-    return st;
+    if (pt_off) pt_off[m] = P.pt_off_h[m];
   }
-  *out = plan;
   return KLDI_OK;
 }
 
@@ -642,13 +1048,19 @@ kldi_status kldi_plan_info(const kldi_plan *plan, kldi_plan_info_t *out) {
   out->n_blocks = P.n_blocks;
   out->n_candidate_tiles = P.n_cand;
   out->n_retained_tiles = P.n_ret;
-  out->retained_fraction = double(P.n_ret) / (double(P.n_tiles) * double(P.n_blocks));
+  double all = 0.0;
+  for (const kldi::MolDev &mo : P.mols_h) all += double(mo.nt) * double(mo.blk1 - mo.blk0);
+  out->retained_fraction = double(P.n_ret) / all;
   out->max_tiles_per_block = P.max_np;
   out->v_segment = P.v_segment;
   out->n_v_items = int64_t(P.items_h.size());
-  out->workspace_bytes = int64_t(P.bytes);
+  out->workspace_bytes = int64_t(P.bytes + P.sched_bytes);
   out->n_grid_chunks = int32_t(P.chunks_h.size());
   out->plan_ms = P.plan_ms;
+  out->n_mol = P.n_mol;
+  out->schedule = P.schedule;
+  out->graph = P.use_graph ? 1 : 0;
+  out->n_x_items = P.n_xitems;
   return KLDI_OK;
 }
 
@@ -659,7 +1071,11 @@ kldi_status kldi_plan_structure(const kldi_plan *plan, int32_t *ao_perm, int64_t
     return KLDI_E_ARG;
   }
   const Plan &P = plan->impl;
-  if (ao_perm) std::copy(P.ao_perm.begin(), P.ao_perm.end(), ao_perm);
+  if (P.n_mol != 1) {
+    kldi::set_error("kldi_plan_structure covers single-molecule plans");
+    return KLDI_E_UNSUPPORTED;
+  }
+  if (ao_perm) std::copy(P.ao_perm.begin(), P.ao_perm.begin() + P.n_ao, ao_perm);
   if (pt_perm) std::copy(P.pt_perm.begin(), P.pt_perm.end(), pt_perm);
   size_t n = size_t(P.n_tiles) * size_t(P.n_blocks);
   if (retained) std::memset(retained, 0, n);
@@ -680,16 +1096,10 @@ kldi_status kldi_eval(kldi_plan *plan, const double *D_dev, double *rho_dev, dou
     return KLDI_E_ARG;
   }
   return kldi::guarded([&] {
-    const Plan &P = plan->impl;
+    Plan &P = plan->impl;
     kldi::check_hip(hipSetDevice(P.device), "hipSetDevice");
-    hipEvent_t *ev = nullptr;
-    if (P.timing) {
-      ev = &plan->impl.events[size_t(P.n_timed % kldi::kTimingSlots) * (KLDI_N_STAGES + 1)];
-      plan->impl.n_timed++;
-    }
-    kldi::check_hip(
-        kldi::launch_eval(P, D_dev, rho_dev, nullptr, exc_dev, vxc_dev, static_cast<hipStream_t>(stream), ev),
-        "eval launch");
+    kldi::IoDev io{D_dev, rho_dev, nullptr, exc_dev, vxc_dev};
+    kldi::run_eval(P, io, vxc_dev != nullptr, static_cast<hipStream_t>(stream), kldi::timing_slot(P));
   });
 }
 
@@ -763,12 +1173,119 @@ kldi_status kldi_eval_grid(kldi_plan *plan, const double *D_dev, double *rho_dev
     return KLDI_E_ARG;
   }
   return kldi::guarded([&] {
-    const Plan &P = plan->impl;
+    Plan &P = plan->impl;
     kldi::check_hip(hipSetDevice(P.device), "hipSetDevice");
-    // E_xc of this call goes to the plan's per-block partials only
-    kldi::check_hip(kldi::launch_eval(P, D_dev, rho_dev, sigma_dev, P.ev.escratch, nullptr,
-                                      static_cast<hipStream_t>(stream), nullptr),
-                    "eval launch");
+    // E_xc of this call goes to the plan's scratch
+    kldi::IoDev io{D_dev, rho_dev, sigma_dev, P.ev.escratch, nullptr};
+    kldi::run_eval(P, io, false, static_cast<hipStream_t>(stream), nullptr);
+  });
+}
+
+kldi_status kldi_plan_graph(kldi_plan *plan, int32_t enable) {
+  if (!plan) {
+    kldi::set_error("plan must not be NULL");
+    return KLDI_E_ARG;
+  }
+  Plan &P = plan->impl;
+  P.use_graph = enable != 0;
+  if (!P.use_graph) kldi::invalidate_graphs(P);
+  return KLDI_OK;
+}
+
+kldi_status kldi_plan_autotune(kldi_plan *plan, const double *D_dev, int32_t reps, void *stream, kldi_tune_t *out) {
+  if (!plan || !D_dev || reps < 0) {
+    kldi::set_error("plan and D must not be NULL; reps >= 0");
+    return KLDI_E_ARG;
+  }
+  return kldi::guarded([&] {
+    Plan &P = plan->impl;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    kldi::check_hip(hipSetDevice(P.device), "hipSetDevice");
+    kldi::check_hip(hipStreamSynchronize(s), "sync");
+    const kldi::TuneKey key = kldi::tune_key(P);
+    kldi_tune_t res{P.v_segment, P.schedule, 0.0, 0};
+    bool cached = false;
+    {
+      std::lock_guard<std::mutex> lk(kldi::g_tune_mu);
+      auto it = kldi::g_tune_cache.find(key);
+      if (it != kldi::g_tune_cache.end()) {
+        cached = true;
+        res.v_segment = it->second.first;
+        res.schedule = it->second.second;
+      }
+    }
+    kldi::invalidate_graphs(P);
+    if (cached || reps == 0) {
+      if (cached && (res.v_segment != P.v_segment || res.schedule != P.schedule))
+        kldi::build_schedule(P, res.v_segment, res.schedule, P.opts.chunk_tiles);
+      if (out) *out = res;
+      return;
+    }
+    // candidates: Vxc tile depths whose partials fit, each with both schedules
+    const auto bc = kldi::block_chunks(P);
+    size_t fr = 0, tot = 0;
+    kldi::check_hip(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    const size_t budget = (fr + P.sched_bytes) / 3;
+    kldi::IoDev io{D_dev, nullptr, nullptr, P.ev.escratch, nullptr};
+    std::vector<double> vbuf;
+    double *vtmp = nullptr;
+    kldi::check_hip(hipMalloc(&vtmp, sizeof(double) * std::max<size_t>(1, size_t(P.mols_h.back().d0) +
+                                                                            size_t(P.mols_h.back().n_ao) * P.mols_h.back().n_ao)),
+                    "hipMalloc");
+    io.vxc = vtmp;
+    hipEvent_t e0, e1;
+    kldi::check_hip(hipEventCreate(&e0), "hipEventCreate");
+    kldi::check_hip(hipEventCreate(&e1), "hipEventCreate");
+    double best = 1e300;
+    int best_seg = P.v_segment, best_sched = P.schedule, tried = 0;
+    const bool was_graph = P.use_graph;
+    P.use_graph = false;
+    try {
+      for (int seg : {8, 16, 32, 64}) {
+        if (size_t(kldi::count_v_items(P, bc, seg)) * 16384 * 8 > budget) continue;
+        for (int sched : {int(KLDI_SCHED_GRID), int(KLDI_SCHED_QUEUE)}) {
+          try {
+            kldi::build_schedule(P, seg, sched, P.opts.chunk_tiles);
+          } catch (const kldi::Error &e) {
+            if (e.code == KLDI_E_OOM) continue;
+            throw;
+          }
+          kldi::run_eval(P, io, true, s, nullptr);   // warm-up
+          kldi::check_hip(hipEventRecord(e0, s), "hipEventRecord");
+          for (int k = 0; k < reps; ++k) kldi::run_eval(P, io, true, s, nullptr);
+          kldi::check_hip(hipEventRecord(e1, s), "hipEventRecord");
+          kldi::check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+          float ms = 0.f;
+          kldi::check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+          ++tried;
+          if (ms / reps < best) {
+            best = ms / reps;
+            best_seg = seg;
+            best_sched = sched;
+          }
+        }
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      (void)hipFree(vtmp);
+      P.use_graph = was_graph;
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(vtmp);
+    P.use_graph = was_graph;
+    kldi::build_schedule(P, best_seg, best_sched, P.opts.chunk_tiles);
+    {
+      std::lock_guard<std::mutex> lk(kldi::g_tune_mu);
+      kldi::g_tune_cache[key] = std::make_pair(best_seg, best_sched);
+    }
+    res.v_segment = best_seg;
+    res.schedule = best_sched;
+    res.ms = best;
+    res.n_tried = tried;
+    if (out) *out = res;
   });
 }
 
@@ -789,6 +1306,6 @@ kldi_status kldi_xc_eval(int32_t xc, const double *rho_dev, const double *sigma_
 
 const char *kldi_last_error(void) { return kldi::g_last_error.c_str(); }
 
-int32_t kldi_version(void) { return 1; }
+int32_t kldi_version(void) { return 2; }
 
 }  // extern "C"

@@ -1,7 +1,11 @@
 // HIP kernels of libkldi for gfx950 (MI355X): block-filtered EXC integration.
 //
+// A plan holds one molecule or a batch of independent molecules in one index space (tiles, blocks,
+// retained tiles and work items numbered consecutively, each belonging to one molecule); every stage
+// below is one launch over all molecules.
+//
 // Per evaluation (one stream, no host synchronisation):
-//   k_reset    clear the executed-pair counters
+//   k_begin    record the caller buffers of the evaluation, clear the counters and work queues
 //   k_dprep    D (caller order, FP64) -> internal AO order, 32x32 tiles, working precision; block
 //              summaries a_pq = max|D_pq| (eq. block_summary_A); non-finite check
 //   k_basis    Phi on the retained (tile, grid block) pairs only (eq. phi_def)
@@ -15,7 +19,11 @@
 //              blocks selected by b_pr * z_qr >= t_d and compacted; M_pq = sum_r Phi_pr Z_qr^T on MFMA
 //   k_vreduce  FP64 sum of the segment partials in fixed order
 //   k_vsym     Vxc = M + M^T (GGA) or mirrored 2M (LDA), back to the caller's AO order
-//   k_esum     E_xc as a fixed-order FP64 sum of per-block partials
+//   k_esum     E_xc of each molecule as a fixed-order FP64 sum of its per-block partials
+// The two GEMM kernels run either one workgroup per work item or as persistent workgroups pulling items
+// from per-XCD queues (kldi_schedule).
+#include <algorithm>
+
 #include "device.h"
 
 namespace kldi {
@@ -59,31 +67,51 @@ __global__ __launch_bounds__(kG) void k_screen(BasisDev B, GridDev g, const int 
 // ------------------------------------------------------------------------------------------------
 // per-evaluation kernels
 // ------------------------------------------------------------------------------------------------
-__global__ void k_reset(unsigned long long *counters) {
+__global__ __launch_bounds__(NT) void k_begin(IoDev *cell, IoDev io, unsigned long long *counters, int *qcnt,
+                                             int nq) {
+  if (threadIdx.x == 0) *cell = io;
   if (threadIdx.x < 4) counters[threadIdx.x] = 0ull;
+  for (int i = threadIdx.x; i < nq; i += NT) qcnt[i] = 0;
 }
 
+// Molecule m with off(mol[m]) <= x < off(mol[m + 1]) for an increasing offset field.
+template <class F>
+__device__ __forceinline__ int find_mol(const MolDev *mol, int n_mol, int64_t x, F &&off) {
+  int lo = 0, hi = n_mol - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off(mol[mid]) <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One workgroup per (p, q) tile pair of a molecule.
 template <class T>
-__global__ __launch_bounds__(NT) void k_dprep(const double *__restrict__ D, const int *__restrict__ perm, int n_ao,
-                                             int n_tiles, T *__restrict__ Dt, double *__restrict__ amax,
-                                             unsigned long long *counters) {
-  const int p = blockIdx.x / n_tiles, q = blockIdx.x % n_tiles;
+__global__ __launch_bounds__(NT) void k_dprep(const MolDev *__restrict__ mol, int n_mol, const IoDev *io,
+                                             const int *__restrict__ perm, T *__restrict__ Dt,
+                                             double *__restrict__ amax, unsigned long long *counters) {
+  const int64_t g = blockIdx.x;
+  const MolDev mo = mol[find_mol(mol, n_mol, g, [](const MolDev &x) { return x.dt0; })];
+  const int loc = int(g - mo.dt0);
+  const int p = loc / mo.nt, q = loc % mo.nt, n_ao = mo.n_ao;
+  const double *D = io->D + mo.d0;
+  const int *pm = perm + size_t(mo.tile0) * kD;
   double m = 0.0;
   int bad = 0;
   for (int e = threadIdx.x; e < kD * kD; e += NT) {
     const int i = p * kD + e / kD, j = q * kD + e % kD;
     double v = 0.0;
-    if (i < n_ao && j < n_ao) v = D[size_t(perm[i]) * n_ao + perm[j]];
+    if (i < n_ao && j < n_ao) v = D[size_t(pm[i]) * n_ao + pm[j]];
     if (!isfinite(v)) bad = 1;
     m = fmax(m, fabs(v));
-    Dt[size_t(blockIdx.x) * (kD * kD) + e] = T(v);
+    Dt[size_t(g) * (kD * kD) + e] = T(v);
   }
   __shared__ double s[4];
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&counters[2], 1ull);
   __syncthreads();
-  if (threadIdx.x == 0) amax[blockIdx.x] = fmax(fmax(s[0], s[1]), fmax(s[2], s[3]));
+  if (threadIdx.x == 0) amax[g] = fmax(fmax(s[0], s[1]), fmax(s[2], s[3]));
 }
 
 template <class T>
@@ -93,8 +121,7 @@ __global__ __launch_bounds__(kG) void k_basis(BasisDev B, GridDev g, StructDev s
   const int64_t ip = int64_t(st.ret_r[k]) * kG + threadIdx.x;
   const double x = g.x[ip], y = g.y[ip], z = g.z[ip];
   T *out = phi + size_t(blockIdx.x) * (kD * kG) + threadIdx.x;
-  const int nvalid = min(kD, B.n_ao - p * kD);
-  for (int a = nvalid; a < kD; ++a) out[a * kG] = T(0);
+  for (int a = B.tile_nv[p]; a < kD; ++a) out[a * kG] = T(0);
   for_tile_aos<false>(B, p, x, y, z, [&](int a, double v, double, double, double) { out[a * kG] = T(v); });
 }
 
@@ -111,6 +138,38 @@ __device__ __forceinline__ void lds_store_unit(T *dst, const uint4 &u) {
   for (int m = 0; m < Units<T>::E; ++m) dst[m] = src[m];
 }
 
+// Persistent schedule: workgroup b serves queue b & 7 (its XCD) first, then the others in turn; a
+// queue's positions lo .. hi - 1 of `order` are handed out by an atomic counter.  Every workgroup
+// leaves once all 8 counters have passed their ends, so the grid always drains.
+struct QArgs {
+  const int *order;        // item ids in queue order (NULL: one workgroup per item)
+  const int64_t *qoff;     // [9] queue boundaries of this launch
+  int *qcnt;               // [8] counters of this launch
+};
+
+template <class F>
+__device__ __forceinline__ void run_items(const QArgs &q, int64_t item0, int64_t n_items, F &&run) {
+  if (q.order == nullptr) {
+    const int64_t il = xcd_remap(blockIdx.x, n_items);
+    if (il < n_items) run(il);
+    return;
+  }
+  __shared__ int s_next;
+  const int x0 = blockIdx.x & 7;
+  for (int k = 0; k < 8; ++k) {
+    const int qx = (x0 + k) & 7;
+    const int64_t lo = q.qoff[qx], hi = q.qoff[qx + 1];
+    for (;;) {
+      if (threadIdx.x == 0) s_next = atomicAdd(&q.qcnt[qx], 1);
+      __syncthreads();
+      const int64_t pos = lo + s_next;
+      __syncthreads();
+      if (pos >= hi) break;
+      run(int64_t(q.order[pos]) - item0);
+    }
+  }
+}
+
 struct XArgs {
   BasisDev B;
   GridDev g;
@@ -125,9 +184,21 @@ struct XArgs {
   double *part;            // [n_items][4][kG] rho, grad rho partial sums, indexed from item0
   unsigned long long *counters;
   double t_b, t_d;
+  QArgs q;
 };
 
 constexpr int NTX = 512;   // threads per X workgroup: 8 waves, each 32 rows x 64 points
+
+// FP32 operands: MFMA steps (K = 4 each) accumulated in FP32 before the FP64 running sum takes them
+#ifndef KLDI_XFLUSH
+#define KLDI_XFLUSH 8
+#endif
+#ifndef KLDI_VFLUSH
+#define KLDI_VFLUSH 8
+#endif
+constexpr int kXFlush = KLDI_XFLUSH;
+constexpr int kVFlush = KLDI_VFLUSH;
+static_assert(8 % kXFlush == 0 && 8 % kVFlush == 0, "flush intervals must divide the 8 steps of a slab");
 
 // One workgroup per (grid block r, chunk c of 4 retained output tiles): X_pr = sum_q D_pq Phi_qr for
 // the 4 tiles p = S_r[4c .. 4c+3], then the chunk's contribution to rho and grad rho.  Wave w owns
@@ -140,30 +211,30 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
   constexpr int STAGES = (sizeof(T) == 4) ? 2 : 1;   // LDS stages of the K loop
-  const int64_t il = xcd_remap(blockIdx.x, A.n_items);
-  if (il >= A.n_items) return;
+  constexpr int kA = 128 * LDA_S, kB = 32 * LDB_S;
+  constexpr int kStageBytes = STAGES * (kA + kB) * int(sizeof(T));
+  static_assert(kStageBytes >= 2 * kD * kG * 8, "two FP64 X tiles must fit the staging area");
+  __shared__ __align__(16) unsigned char s_raw[kStageBytes];
+  __shared__ int s_p[kMaxNp];
+  __shared__ int s_list[kMaxNp];
+  __shared__ int s_w[8];
+  __shared__ double s_acc[2][4][kG];
+  run_items(A.q, A.item0, A.n_items, [&](int64_t il) {
   const int64_t it = A.item0 + il;
   const int64_t r = A.xit_r[it];
   const int c = A.xit_c[it];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int u = w & 3, h = w >> 2;
-  const int n_tiles = A.B.n_tiles;
+  const MolDev mo = A.st.mol[A.st.blk_mol[r]];
   const int64_t k0 = A.st.blk_off[r];
   const int np = int(A.st.blk_off[r + 1] - k0);
   const T *Dt = static_cast<const T *>(A.Dt);
   const T *phi = static_cast<const T *>(A.phi) - size_t(A.ret0) * (kD * kG);   // indexed by retained tile
-
-  constexpr int kA = 128 * LDA_S, kB = 32 * LDB_S;
-  constexpr int kStageBytes = STAGES * (kA + kB) * int(sizeof(T));
-  static_assert(kStageBytes >= 2 * kD * kG * 8, "two FP64 X tiles must fit the staging area");
-  __shared__ __align__(16) unsigned char s_raw[kStageBytes];
+  // (p, q) tile pair of the molecule -> its position in Dt / amax
+  auto dtile = [&](int p, int q) { return size_t(mo.dt0) + size_t(p - mo.tile0) * mo.nt + (q - mo.tile0); };
   T *sA = reinterpret_cast<T *>(s_raw);                 // [STAGES][kA]
   T *sB = sA + STAGES * kA;                              // [STAGES][kB]
   double *Xs = reinterpret_cast<double *>(s_raw);        // [2][32][kG] in the epilogue
-  __shared__ int s_p[kMaxNp];
-  __shared__ int s_list[kMaxNp];
-  __shared__ int s_w[8];
-  __shared__ double s_acc[2][4][kG];
 
   for (int t = tid; t < np; t += NTX) s_p[t] = A.st.ret_p[k0 + t];
   for (int e = tid; e < 8 * kG; e += NTX) (&s_acc[0][0][0])[e] = 0.0;
@@ -182,7 +253,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
 #pragma unroll
       for (int ww = 0; ww < 4; ++ww) {
         if (4 * c + ww < np) {
-          const double a = A.amax[size_t(s_p[4 * c + ww]) * n_tiles + q];
+          const double a = A.amax[dtile(s_p[4 * c + ww], q)];
           if (a >= A.t_b && a * bq >= A.t_d) mask |= 1 << ww;
         }
       }
@@ -229,7 +300,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
       const int un = tid + NTX * m, ww = un / UA, uu = un % UA;
       ra[m] = make_uint4(0, 0, 0, 0);
       if (4 * c + ww < np)
-        ra[m] = reinterpret_cast<const uint4 *>(Dt + (size_t(s_p[4 * c + ww]) * n_tiles + q) * (kD * kD))[uu];
+        ra[m] = reinterpret_cast<const uint4 *>(Dt + dtile(s_p[4 * c + ww], q) * (kD * kD))[uu];
     }
     const uint4 *src = reinterpret_cast<const uint4 *>(phi + size_t(k0 + t) * (kD * kG));
 #pragma unroll
@@ -272,16 +343,16 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
           acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
           acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
         }
-      }
-      if (sizeof(T) == 4) {
+        if (sizeof(T) == 4 && kk % kXFlush == kXFlush - 1) {
 #pragma unroll
-        for (int ti = 0; ti < 2; ++ti)
+          for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-          for (int tj = 0; tj < 4; ++tj) {
+            for (int tj = 0; tj < 4; ++tj) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
-            acc[ti][tj] = acc_t{};
-          }
+              for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
+              acc[ti][tj] = acc_t{};
+            }
+        }
       }
     }
     if (STAGES == 1) {
@@ -347,6 +418,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   }
   double pd = wave_sum(double(pairs));
   if (l == 0 && pd > 0) atomicAdd(&A.counters[0], (unsigned long long)(pd + 0.5));
+  });
 }
 
 // One workgroup per grid block: rho and grad rho as fixed-order FP64 sums over the chunk partials,
@@ -369,8 +441,9 @@ __global__ __launch_bounds__(kG) void k_xfunc(FArgs A) {
   const Xc f = xc_eval(A.xc, s[0], sigma, A.rho_cut);
   const double wgt = A.g.w[ip];
   const int64_t o = A.g.orig[ip];
-  if (A.rho_out && o >= 0) A.rho_out[o] = s[0];
-  if (A.sigma_out && o >= 0) A.sigma_out[o] = sigma;
+  double *rho_out = A.io->rho, *sigma_out = A.io->sigma;
+  if (rho_out && o >= 0) rho_out[o] = s[0];
+  if (sigma_out && o >= 0) sigma_out[o] = sigma;
   double *cf = A.coef + size_t(ip) * 4;
   cf[0] = 0.5 * wgt * f.vr;
   cf[1] = 2.0 * wgt * f.vs * s[1];
@@ -402,8 +475,7 @@ __global__ __launch_bounds__(kG) void k_zform(BasisDev B, GridDev g, StructDev s
   double zm = 0.0;
   if (GGA) {
     const double c1x = cf[1], c1y = cf[2], c1z = cf[3];
-    const int nvalid = min(kD, B.n_ao - p * kD);
-    for (int a = nvalid; a < kD; ++a) out[a * kG] = T(0);
+    for (int a = B.tile_nv[p]; a < kD; ++a) out[a * kG] = T(0);
     for_tile_aos<true>(B, p, g.x[ip], g.y[ip], g.z[ip], [&](int a, double v, double gx, double gy, double gz) {
       const T zt = T(c0 * v + c1x * gx + c1y * gy + c1z * gz);
       out[a * kG] = zt;
@@ -426,12 +498,14 @@ __global__ __launch_bounds__(kG) void k_zform(BasisDev B, GridDev g, StructDev s
 
 struct VMaskArgs {
   StructDev st;
-  const int *cinfo;        // [n_blocks * n_chunks]: (first position in S_r) << 4 | retained 4-bit mask
-  const int *pair_pq;      // [2 * n_pairs]
-  int n_pairs, n_chunks;
+  const int *cinfo;        // per (block, chunk of its molecule): (first position in S_r) << 4 | 4-bit mask
+  const int64_t *cioff;    // [n_blocks+1] first cinfo entry of each block
+  const int64_t *vmoff;    // [n_blocks+1] first vmask entry of each block
+  int64_t vm_base;         // vmoff of the launch's first block (the vmask slice starts there)
+  const int *pair_info;    // [3 * n_pairs] (row chunk, column chunk, molecule)
   const double *zmax;
   int64_t blk0;            // first block of this launch
-  unsigned short *vmask;   // [blocks of the launch * n_pairs]
+  unsigned short *vmask;   // mask slice of the launch
   double t_b, t_d;
   int upper_only;          // LDA: only tiles p <= q are formed (Vxc is mirrored)
 };
@@ -452,9 +526,11 @@ __global__ __launch_bounds__(NT) void k_vmask(VMaskArgs A) {
     s_z[t] = A.zmax[k0 + t];
   }
   __syncthreads();
-  const int *ci = A.cinfo + size_t(r) * A.n_chunks;
-  for (int pr = threadIdx.x; pr < A.n_pairs; pr += NT) {
-    const int pc = A.pair_pq[2 * pr], qc = A.pair_pq[2 * pr + 1];
+  const MolDev mo = A.st.mol[A.st.blk_mol[r]];
+  const int *ci = A.cinfo + A.cioff[r];
+  unsigned short *out = A.vmask + (A.vmoff[r] - A.vm_base);
+  for (int pr = threadIdx.x; pr < mo.npairs; pr += NT) {
+    const int pc = A.pair_info[3 * (mo.pair0 + pr)], qc = A.pair_info[3 * (mo.pair0 + pr) + 1];
     const int ip = ci[pc], iq = ci[qc];
     int mask = 0;
     if ((ip & 15) && (iq & 15)) {
@@ -471,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_vmask(VMaskArgs A) {
         }
       }
     }
-    A.vmask[size_t(blockIdx.x) * A.n_pairs + pr] = (unsigned short)mask;
+    out[pr] = (unsigned short)mask;
   }
 }
 
@@ -479,15 +555,17 @@ struct VArgs {
   StructDev st;
   const VItem *items;
   int64_t item0, n_items;  // the items of this launch
-  int64_t blk0, ret0;      // first block of the vmask slice; first retained tile of the workspaces
+  int64_t ret0;            // first retained tile of the workspaces
   const int *cinfo;
-  int n_chunks, n_pairs;
+  const int64_t *cioff, *vmoff;
+  int64_t vm_base;         // vmoff of the launch's first block
   const unsigned short *vmask;
   const void *phi;
   const void *zws;
   double *vpart;
   int *vflag;              // [n_items] 1 if the item wrote a partial
   unsigned long long *counters;
+  QArgs q;
 };
 
 constexpr int NTV = 512;   // threads per Vxc workgroup: 8 waves, each 32 rows x 64 columns
@@ -500,16 +578,6 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   typedef Mma<T> M;
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
-  const int64_t il = xcd_remap(blockIdx.x, A.n_items);
-  if (il >= A.n_items) return;
-  const int64_t item = A.item0 + il;
-  const VItem it = A.items[item];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int u = w & 3, h = w >> 2;
-  const T *phi = static_cast<const T *>(A.phi) - size_t(A.ret0) * (kD * kG);   // indexed by retained tile
-  const T *zws = static_cast<const T *>(A.zws) - size_t(A.ret0) * (kD * kG);
-  const int pr = it.pair;
-
   constexpr int kS = 128 * LDA_S;  // one A or B stage (4 tiles x 32 rows x 32 points)
   __shared__ __align__(16) T sA[2 * kS];
   __shared__ __align__(16) T sB[2 * kS];
@@ -517,6 +585,13 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   __shared__ int s_ip[NTV], s_iq[NTV];
   __shared__ long long s_bo[NTV];
   __shared__ int s_w[8];
+  run_items(A.q, A.item0, A.n_items, [&](int64_t il) {
+  const int64_t item = A.item0 + il;
+  const VItem it = A.items[item];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int u = w & 3, h = w >> 2;
+  const T *phi = static_cast<const T *>(A.phi) - size_t(A.ret0) * (kD * kG);   // indexed by retained tile
+  const T *zws = static_cast<const T *>(A.zws) - size_t(A.ret0) * (kD * kG);
 
   acc_t acc[2][4];
   double dacc[2][4][4];
@@ -534,7 +609,7 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   for (int base = it.r0; base < it.r1; base += NTV) {
     const int r = base + tid;
     int mask = 0;
-    if (r < it.r1) mask = A.vmask[size_t(r - A.blk0) * A.n_pairs + pr];
+    if (r < it.r1) mask = A.vmask[A.vmoff[r] - A.vm_base + it.lpair];
     // exclusive prefix sum over the 8 waves (parallel addressing)
     const unsigned long long bal = __ballot(mask != 0);
     const int before = __popcll(bal & ((1ull << l) - 1ull));
@@ -547,8 +622,9 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
     }
     if (mask) {
       s_m[pos] = mask;
-      s_ip[pos] = A.cinfo[size_t(r) * A.n_chunks + it.pc];
-      s_iq[pos] = A.cinfo[size_t(r) * A.n_chunks + it.qc];
+      const int64_t cb = A.cioff[r];
+      s_ip[pos] = A.cinfo[cb + it.pc];
+      s_iq[pos] = A.cinfo[cb + it.qc];
       s_bo[pos] = A.st.blk_off[r];
       pairs += __popc(mask);
     }
@@ -618,18 +694,18 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
               acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
             }
           }
-        }
-        if (sizeof(T) == 4) {
-          // FP32 accumulation spans one 32-point slab; the running sum over slabs and grid blocks
-          // is FP64
+          if (sizeof(T) == 4 && kk % kVFlush == kVFlush - 1) {
+            // FP32 accumulation spans 4 kVFlush points; the running sum over those spans, the
+            // slabs and the grid blocks is FP64
 #pragma unroll
-          for (int ti = 0; ti < 2; ++ti)
+            for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < 4; ++tj) {
+              for (int tj = 0; tj < 4; ++tj) {
 #pragma unroll
-              for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
-              acc[ti][tj] = acc_t{};
-            }
+                for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
+                acc[ti][tj] = acc_t{};
+              }
+          }
         }
       }
       if (st + 1 < nst) stash(buf ^ 1);
@@ -640,6 +716,8 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
     if (tid == 0) A.vflag[item] = 0;
     return;
   }
+  // every thread has read the entry metadata of the last compaction round (the K loop ends with a
+  // barrier), so the next item of a persistent workgroup may overwrite it
   double *out = A.vpart + size_t(item) * (128 * 128);
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
@@ -653,11 +731,13 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   if (tid == 0) A.vflag[item] = 1;
   double pd = wave_sum(double(pairs));
   if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
+  });
 }
 
-__global__ __launch_bounds__(NT) void k_vreduce(const int *pair_ptr, const int *pair_items, const int *pair_pq,
-                                               const int *__restrict__ vflag, const double *__restrict__ vpart,
-                                               double *__restrict__ mfull, int ld) {
+// One workgroup row per chunk pair (all molecules): FP64 sum of its segment partials in segment order.
+__global__ __launch_bounds__(NT) void k_vreduce(const int *pair_ptr, const int *pair_items, const int *pair_info,
+                                               const MolDev *mol, const int *__restrict__ vflag,
+                                               const double *__restrict__ vpart, double *__restrict__ mfull) {
   const int pr = blockIdx.x;
   const int e = blockIdx.y * NT + threadIdx.x;  // 0 .. 16383
   const int i = e >> 7, j = e & 127;
@@ -666,16 +746,23 @@ __global__ __launch_bounds__(NT) void k_vreduce(const int *pair_ptr, const int *
     const int itm = pair_items[k];
     if (vflag[itm]) s += vpart[size_t(itm) * 16384 + e];
   }
-  const int pc = pair_pq[2 * pr], qc = pair_pq[2 * pr + 1];
-  mfull[size_t(128 * pc + i) * ld + 128 * qc + j] = s;
+  const int pc = pair_info[3 * pr], qc = pair_info[3 * pr + 1];
+  const MolDev mo = mol[pair_info[3 * pr + 2]];
+  mfull[size_t(mo.mf0) + size_t(128 * pc + i) * mo.ld + 128 * qc + j] = s;
 }
 
-__global__ __launch_bounds__(NT) void k_vsym(const double *__restrict__ mfull, int ld, const int *__restrict__ perm,
-                                            int n_ao, int gga, double *__restrict__ vxc) {
-  const int i = blockIdx.y;
-  const int j = blockIdx.x * NT + threadIdx.x;
+// Vxc = M + M^T (GGA) or mirrored 2M (LDA), back to the caller's AO order.  One workgroup per
+// (stacked AO row, group of NT columns).
+__global__ __launch_bounds__(NT) void k_vsym(const MolDev *mol, int n_mol, int ncol, const double *__restrict__ mfull,
+                                            const int *__restrict__ perm, int gga, const IoDev *io) {
+  const int64_t g = blockIdx.x / ncol;
+  const int j = (blockIdx.x % ncol) * NT + threadIdx.x;
+  const MolDev mo = mol[find_mol(mol, n_mol, g, [](const MolDev &x) { return x.row0; })];
+  const int i = int(g - mo.row0), n_ao = mo.n_ao;
   if (j >= n_ao) return;
-  const double mij = mfull[size_t(i) * ld + j], mji = mfull[size_t(j) * ld + i];
+  const double *mf = mfull + mo.mf0;
+  const int *pm = perm + size_t(mo.tile0) * kD;
+  const double mij = mf[size_t(i) * mo.ld + j], mji = mf[size_t(j) * mo.ld + i];
   double v;
   if (gga) {
     v = mij + mji;
@@ -683,27 +770,35 @@ __global__ __launch_bounds__(NT) void k_vsym(const double *__restrict__ mfull, i
     const int p = i / kD, q = j / kD;
     v = (p < q) ? 2.0 * mij : (p > q ? 2.0 * mji : mij + mji);
   }
-  vxc[size_t(perm[i]) * n_ao + perm[j]] = v;
+  io->vxc[size_t(mo.d0) + size_t(pm[i]) * n_ao + pm[j]] = v;
 }
 
-__global__ __launch_bounds__(NT) void k_esum(const double *__restrict__ eblk, int64_t n, double *exc) {
+// One workgroup per molecule: E_xc as a fixed-order FP64 sum of its block partials.
+__global__ __launch_bounds__(NT) void k_esum(const MolDev *mol, const double *__restrict__ eblk, const IoDev *io) {
+  const MolDev mo = mol[blockIdx.x];
   __shared__ double s[NT];
   double a = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += NT) a += eblk[i];
+  for (int64_t i = mo.blk0 + threadIdx.x; i < mo.blk1; i += NT) a += eblk[i];
   s[threadIdx.x] = a;
   __syncthreads();
   for (int k = NT / 2; k > 0; k >>= 1) {
     if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) exc[0] = s[0];
+  if (threadIdx.x == 0) io->exc[blockIdx.x] = s[0];
+}
+
+// Persistent grid of a GEMM launch: resident workgroups over the chip, at most one per item, a
+// multiple of 8 so every XCD queue has servers.
+int64_t persistent_grid(int occ, int n_cu, int64_t n_items) {
+  const int64_t full = int64_t(std::max(occ, 1)) * std::max(n_cu, 8);
+  return 8 * ((std::min(full, n_items) + 7) / 8);
 }
 
 template <class T>
-hipError_t eval_typed(const Plan &P, const double *D, double *rho, double *sigma, double *exc, double *vxc,
-                      hipStream_t s, hipEvent_t *ev) {
+hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
   const EvalDev &E = P.ev;
-  const int nt = P.n_tiles;
+  const bool queue = P.schedule == KLDI_SCHED_QUEUE;
   // stage events: per stage when the grid is processed in one chunk; with several chunks the
   // stages interleave and everything between the D preparation and the final sums is one stage
   const bool one = P.chunks_h.size() == 1;
@@ -711,15 +806,16 @@ hipError_t eval_typed(const Plan &P, const double *D, double *rho, double *sigma
     if (ev) (void)hipEventRecord(ev[i], s);
   };
   mark(0);
-  k_reset<<<1, 64, 0, s>>>(E.counters);
-  k_dprep<T><<<nt * nt, NT, 0, s>>>(D, P.ao_perm_d, P.n_ao, nt, static_cast<T *>(E.Dt), E.amax, E.counters);
+  k_dprep<T><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, static_cast<T *>(E.Dt), E.amax, E.counters);
   mark(1);
   if (!one) {
     mark(2);
     mark(3);
     mark(4);
   }
-  for (const GridChunk &C : P.chunks_h) {
+  const int occ_x = queue ? occupancy_x(P) : 0, occ_v = queue ? occupancy_v(P) : 0;
+  for (size_t ci = 0; ci < P.chunks_h.size(); ++ci) {
+    const GridChunk &C = P.chunks_h[ci];
     const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nxit = C.xit1 - C.xit0, nvit = C.vit1 - C.vit0;
     if (nret > 0) k_basis<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, static_cast<T *>(E.phi));
     if (one) mark(2);
@@ -739,8 +835,13 @@ hipError_t eval_typed(const Plan &P, const double *D, double *rho, double *sigma
     xa.counters = E.counters;
     xa.t_b = P.opts.t_b;
     xa.t_d = P.opts.t_d;
+    xa.q = QArgs{nullptr, nullptr, nullptr};
+    int64_t gx = 8 * ((nxit + 7) / 8);
+    if (queue) {
+      xa.q = QArgs{P.xq.order, P.xq.qoff + 9 * ci, E.qcnt + 16 * ci};
+      gx = persistent_grid(occ_x, P.n_cu, nxit);
+    }
     if (nxit > 0) {
-      const int64_t gx = 8 * ((nxit + 7) / 8);
       if (P.gga)
         k_xgemm<T, true><<<gx, NTX, 0, s>>>(xa);
       else
@@ -755,19 +856,18 @@ hipError_t eval_typed(const Plan &P, const double *D, double *rho, double *sigma
     fa.part = E.xpart;
     fa.coef = E.coef;
     fa.eblk = E.eblk;
-    fa.rho_out = rho;
-    fa.sigma_out = sigma;
+    fa.io = E.io;
     fa.counters = E.counters;
     fa.rho_cut = P.opts.rho_cut;
     fa.xc = P.opts.xc;
     fa.gga = P.gga ? 1 : 0;
     if (nblk > 0) {
       if (P.has_mlp)
-        mlp_launch_xfunc(fa, P.mlp, nblk, s);
+        (void)mlp_launch_xfunc(fa, P.mlp, nblk, s);
       else
         k_xfunc<<<nblk, kG, 0, s>>>(fa);
     }
-    if (vxc && nret > 0) {
+    if (want_v && nret > 0) {
       if (P.gga)
         k_zform<T, true><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, static_cast<const T *>(E.phi),
                                              static_cast<T *>(E.zws), E.zmax);
@@ -776,13 +876,14 @@ hipError_t eval_typed(const Plan &P, const double *D, double *rho, double *sigma
                                               static_cast<T *>(E.zws), E.zmax);
     }
     if (one) mark(4);
-    if (vxc && nblk > 0) {
+    if (want_v && nblk > 0) {
       VMaskArgs ma;
       ma.st = P.st;
       ma.cinfo = P.cinfo;
-      ma.pair_pq = P.pair_pq;
-      ma.n_pairs = P.n_pairs;
-      ma.n_chunks = P.n_chunks;
+      ma.cioff = P.cioff;
+      ma.vmoff = P.vmoff;
+      ma.vm_base = P.vmoff_h[C.blk0];
+      ma.pair_info = P.pair_info;
       ma.zmax = E.zmax;
       ma.blk0 = C.blk0;
       ma.vmask = E.vmask;
@@ -795,29 +896,54 @@ hipError_t eval_typed(const Plan &P, const double *D, double *rho, double *sigma
       va.items = P.items;
       va.item0 = C.vit0;
       va.n_items = nvit;
-      va.blk0 = C.blk0;
       va.ret0 = C.ret0;
       va.cinfo = P.cinfo;
-      va.n_chunks = P.n_chunks;
-      va.n_pairs = P.n_pairs;
+      va.cioff = P.cioff;
+      va.vmoff = P.vmoff;
+      va.vm_base = P.vmoff_h[C.blk0];
       va.vmask = E.vmask;
       va.phi = E.phi;
       va.zws = E.zws;
       va.vpart = E.vpart;
       va.vflag = E.vflag;
       va.counters = E.counters;
-      if (nvit > 0) k_vgemm<T><<<8 * ((nvit + 7) / 8), NTV, 0, s>>>(va);
+      va.q = QArgs{nullptr, nullptr, nullptr};
+      int64_t gv = 8 * ((nvit + 7) / 8);
+      if (queue) {
+        va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci, E.qcnt + 16 * ci + 8};
+        gv = persistent_grid(occ_v, P.n_cu, nvit);
+      }
+      if (nvit > 0) k_vgemm<T><<<gv, NTV, 0, s>>>(va);
     }
   }
   mark(5);
-  if (vxc) {
-    const int ld = P.n_chunks * 128;
-    k_vreduce<<<dim3(P.n_pairs, 64), NT, 0, s>>>(P.pair_ptr, P.pair_items, P.pair_pq, E.vflag, E.vpart, E.mfull, ld);
-    k_vsym<<<dim3((P.n_ao + NT - 1) / NT, P.n_ao), NT, 0, s>>>(E.mfull, ld, P.ao_perm_d, P.n_ao, P.gga ? 1 : 0, vxc);
+  if (want_v) {
+    k_vreduce<<<dim3(P.n_pairs, 64), NT, 0, s>>>(P.pair_ptr, P.pair_items, P.pair_info, P.st.mol, E.vflag, E.vpart,
+                                                E.mfull);
+    const int ncol = (P.max_nao + NT - 1) / NT;
+    k_vsym<<<int64_t(P.n_ao) * ncol, NT, 0, s>>>(P.st.mol, P.n_mol, ncol, E.mfull, P.ao_perm_d, P.gga ? 1 : 0, E.io);
   }
-  k_esum<<<1, NT, 0, s>>>(E.eblk, P.n_blocks, exc);
+  k_esum<<<P.n_mol, NT, 0, s>>>(P.st.mol, E.eblk, E.io);
   mark(6);
   return hipGetLastError();
+}
+
+template <class T, bool GGA>
+int occ_x_typed() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_xgemm<T, GGA>), NTX, 0) !=
+      hipSuccess)
+    n = 1;
+  return std::max(n, 1);
+}
+
+template <class T>
+int occ_v_typed() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_vgemm<T>), NTV, 0) !=
+      hipSuccess)
+    n = 1;
+  return std::max(n, 1);
 }
 
 }  // namespace
@@ -829,10 +955,26 @@ hipError_t launch_screen(const BasisDev &b, const GridDev &g, const int *cand_p,
   return hipGetLastError();
 }
 
-hipError_t launch_eval(const Plan &P, const double *D, double *rho, double *sigma, double *exc, double *vxc,
-                       hipStream_t s, hipEvent_t *ev) {
-  if (P.opts.prec == KLDI_PREC_FP64) return eval_typed<double>(P, D, rho, sigma, exc, vxc, s, ev);
-  return eval_typed<float>(P, D, rho, sigma, exc, vxc, s, ev);
+hipError_t launch_begin(const Plan &P, const IoDev &io, hipStream_t s) {
+  k_begin<<<1, NT, 0, s>>>(P.ev.io, io, P.ev.counters, P.ev.qcnt, int(16 * P.chunks_h.size()));
+  return hipGetLastError();
+}
+
+hipError_t launch_body(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
+  if (P.opts.prec == KLDI_PREC_FP64) return body_typed<double>(P, want_v, s, ev);
+  return body_typed<float>(P, want_v, s, ev);
+}
+
+int occupancy_x(const Plan &P) {
+  const bool d = P.opts.prec == KLDI_PREC_FP64;
+  static const int o[4] = {occ_x_typed<float, false>(), occ_x_typed<float, true>(), occ_x_typed<double, false>(),
+                           occ_x_typed<double, true>()};
+  return o[2 * (d ? 1 : 0) + (P.gga ? 1 : 0)];
+}
+
+int occupancy_v(const Plan &P) {
+  static const int o[2] = {occ_v_typed<float>(), occ_v_typed<double>()};
+  return o[P.opts.prec == KLDI_PREC_FP64 ? 1 : 0];
 }
 
 }  // namespace kldi

@@ -27,6 +27,33 @@ struct MlpDev {
   double rho_min;                 // below this density the analytic functional is used
 };
 
+// A plan holds one molecule or a batch of independent molecules in one index space: the AO tiles,
+// grid blocks, retained tiles and work items of all molecules are numbered consecutively, and every
+// tile or block belongs to exactly one molecule.  Per-molecule offsets:
+struct MolDev {
+  int tile0, nt;          // first AO tile, AO tiles
+  int nc;                 // chunks of 4 tiles
+  int pair0, npairs;      // Vxc chunk pairs (global index range)
+  int n_ao;               // AOs
+  int ld;                 // leading dimension of the molecule's M workspace (nc * 128)
+  int pad_;
+  int64_t row0;           // first row of the molecule in the stacked caller AO index (sum of n_ao)
+  int64_t dt0;            // first (p, q) tile pair in Dt / amax (sum of nt^2)
+  int64_t d0;             // first element of D and Vxc in the packed caller arrays (sum of n_ao^2)
+  int64_t blk0, blk1;     // grid blocks
+  int64_t mf0;            // first element of the M workspace
+};
+
+// Caller buffers of the running evaluation.  k_begin writes them to device memory at the start of
+// each evaluation, so a captured graph of the remaining kernels serves any buffers.
+struct IoDev {
+  const double *D;        // packed D (molecule m at MolDev::d0, n_ao x n_ao row-major)
+  double *rho;            // packed rho in caller point order, or NULL
+  double *sigma;          // packed sigma, or NULL
+  double *exc;            // [n_mol]
+  double *vxc;            // packed Vxc, or NULL
+};
+
 // Device view of the basis in internal (reordered) AO order.
 struct BasisDev {
   const double *sh_xyz;    // [n_shells*3] centre of each internal shell
@@ -38,29 +65,30 @@ struct BasisDev {
   const int *ao_shell;     // [n_ao_pad] internal shell of each AO, -1 on padding rows
   const int *ao_comp;      // [n_ao_pad] cartesian powers packed lx | ly<<2 | lz<<4
   const int *tile_sh;      // [n_tiles*2] shells overlapping each tile
-  int n_ao;
-  int n_tiles;
+  const int *tile_nv;      // [n_tiles] AOs of each tile (32 but on a molecule's last tile)
 };
 
 // Device view of the reordered, padded grid.
 struct GridDev {
   const double *x, *y, *z, *w;   // [n_pad]
-  const int64_t *orig;           // [n_pad] caller index, -1 on padding
+  const int64_t *orig;           // [n_pad] caller index (packed over molecules), -1 on padding
   int64_t n_blocks;
 };
 
-// Retained block structure (BCS(C) by grid block, plus a dense (block, tile) -> position map).
+// Retained block structure (BCS(C) by grid block) and the molecule table.
 struct StructDev {
   const int64_t *blk_off;  // [n_blocks+1] first retained tile of each block
   const int *ret_p;        // [n_ret] AO tile of each retained tile
   const int *ret_r;        // [n_ret] grid block of each retained tile
-  const int *idx_map;      // [n_blocks*n_tiles] position within S_r or -1
   const double *bphi;      // [n_ret] max |Phi| of the tile
+  const int *blk_mol;      // [n_blocks] molecule of each block
+  const MolDev *mol;       // [n_mol]
+  int n_mol;
 };
 
 struct EvalDev {
-  void *Dt;                // [n_tiles^2 * 1024] internal tiled D, working precision
-  double *amax;            // [n_tiles^2] max |D_pq|
+  void *Dt;                // [sum nt^2 * 1024] internal tiled D, working precision
+  double *amax;            // [sum nt^2] max |D_pq|
   void *phi;               // [max chunk retained tiles * 4096] Phi workspace, working precision
   void *zws;               // [max chunk retained tiles * 4096] Z workspace
   double *xpart;           // [max chunk X items * 4 * 128] rho / grad rho partials of each X work item
@@ -69,10 +97,12 @@ struct EvalDev {
   double *eblk;            // [n_blocks]
   double *vpart;           // [n_items * 16384]
   int *vflag;              // [n_items] 1 if the item wrote a partial
-  unsigned short *vmask;   // [max chunk blocks * n_pairs] executable tile pairs of each chunk pair
-  double *mfull;           // [(n_chunks*128)^2]
+  unsigned short *vmask;   // [max chunk mask entries] executable tile pairs of each (block, chunk pair)
+  double *mfull;           // [sum (nc*128)^2]
   unsigned long long *counters;  // [4]: pairs X, pairs V, nonfinite flag, points on the surrogate
-  double *escratch;        // [1] E_xc of kldi_eval_grid
+  double *escratch;        // [n_mol] E_xc of kldi_eval_grid
+  IoDev *io;               // [1] caller buffers of the running evaluation
+  int *qcnt;               // [n_gchunks * 16] work-queue counters (X: 8 per chunk, V: 8 per chunk)
 };
 
 // A range of grid blocks processed with one filling of the Phi / Z workspaces.
@@ -84,30 +114,48 @@ struct GridChunk {
 };
 
 struct VItem {
-  int pc, qc;
-  int r0, r1;
-  int pair;      // index of (pc, qc) in the pair table
-  int pad;
+  int pc, qc;    // row and column chunk (molecule-local)
+  int r0, r1;    // grid blocks of the segment
+  int pair;      // global index of (pc, qc) in the pair table
+  int lpair;     // index of (pc, qc) among the molecule's pairs
+};
+
+// Work order of the persistent GEMM kernels: each grid chunk's items are split into 8 queues (one
+// per XCD, contiguous in blocks / segments for L2 sharing), each ordered by decreasing cost.
+struct Queues {
+  int *order = nullptr;          // [n_items] item ids in queue order
+  int64_t *qoff = nullptr;       // [n_gchunks * 9] queue boundaries (positions in order)
 };
 
 struct Plan {
   int device = 0;
+  int n_cu = 0;
   kldi_opts opts{};
   bool gga = false;
-  int n_ao = 0, n_tiles = 0, n_chunks = 0, n_shells = 0;
+  int n_mol = 0;
+  int n_ao = 0, n_tiles = 0, n_shells = 0;   // totals over molecules
   int64_t n_points = 0, n_blocks = 0, n_pad = 0, n_ret = 0, n_cand = 0;
-  int max_np = 0;
+  int64_t n_dt = 0, n_mfull = 0;
+  int max_np = 0, max_nao = 0;
   int v_segment = 0;
-  std::vector<int32_t> ao_perm;       // internal -> caller
-  std::vector<int64_t> pt_perm;       // internal -> caller
+  int schedule = KLDI_SCHED_GRID;
+  std::vector<MolDev> mols_h;
+  std::vector<int32_t> ao_perm;       // internal AO (padded, all molecules) -> caller AO within its molecule
+  std::vector<int64_t> pt_perm;       // internal point -> caller point (single-molecule plans)
+  std::vector<int64_t> pt_off_h;      // [n_mol+1] first caller point of each molecule
   std::vector<int64_t> blk_off_h;
   std::vector<int32_t> ret_p_h;
+  std::vector<int32_t> blk_mol_h;
   std::vector<double> bphi_h;
+  std::vector<int64_t> cioff_h, vmoff_h;
+  std::vector<int> cinfo_h;
   std::vector<VItem> items_h;
   int n_pairs = 0;
   double plan_ms = 0.0;
   size_t bytes = 0;
-  std::vector<void *> allocs;
+  std::vector<void *> allocs;         // held for the plan's life
+  std::vector<void *> sched_allocs;   // work lists and workspaces of the current schedule
+  size_t sched_bytes = 0;
   // device
   BasisDev basis{};
   GridDev grid{};
@@ -122,9 +170,12 @@ struct Plan {
   VItem *items = nullptr;
   int *pair_ptr = nullptr;   // [n_pairs+1] CSR over pair_items
   int *pair_items = nullptr; // item indices grouped by chunk pair, segment order
-  int *pair_pq = nullptr;    // [2*n_pairs] (row chunk, column chunk) of each pair
-  int *cinfo = nullptr;      // [n_blocks*n_chunks] (first position in S_r) << 4 | retained mask
+  int *pair_info = nullptr;  // [3*n_pairs] (row chunk, column chunk, molecule) of each pair
+  int *cinfo = nullptr;      // per (block, chunk of its molecule): (first position in S_r) << 4 | mask
+  int64_t *cioff = nullptr;  // [n_blocks+1] first cinfo entry of each block
+  int64_t *vmoff = nullptr;  // [n_blocks+1] first vmask entry of each block
   int32_t *ao_perm_d = nullptr;
+  Queues xq, vq;
   // functional surrogate attached with kldi_plan_attach_mlp
   bool has_mlp = false;
   MlpDev mlp{};
@@ -132,18 +183,30 @@ struct Plan {
   bool timing = false;
   int n_timed = 0;
   std::vector<hipEvent_t> events;
+  // captured launch graphs of one evaluation after k_begin: [0] without Vxc, [1] with Vxc
+  bool use_graph = false;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
 };
 
 constexpr int kTimingSlots = 256;
 
 // error reporting (host.cpp)
 void set_error(const std::string &msg);
+// drops the captured graphs (after a change of what one evaluation launches)
+void invalidate_graphs(Plan &P);
 
 // launchers (kernels.hip); each returns hipSuccess or the launch error
 hipError_t launch_screen(const BasisDev &b, const GridDev &g, const int *cand_p, const int64_t *cand_r,
                          int64_t n_cand, bool gga, double *out_b, double *out_g, hipStream_t s);
-hipError_t launch_eval(const Plan &P, const double *D, double *rho, double *sigma, double *exc, double *vxc,
-                       hipStream_t s, hipEvent_t *ev /* KLDI_N_STAGES + 1 events, or NULL */);
+// k_begin: record the caller buffers of this evaluation and clear its counters and queues
+hipError_t launch_begin(const Plan &P, const IoDev &io, hipStream_t s);
+// everything after k_begin (captured into a graph when the plan runs in graph mode)
+hipError_t launch_body(const Plan &P, bool want_v, hipStream_t s,
+                       hipEvent_t *ev /* KLDI_N_STAGES + 1 events, or NULL */);
+// resident workgroups per CU of the persistent GEMM kernels at the plan's precision
+int occupancy_x(const Plan &P);
+int occupancy_v(const Plan &P);
 hipError_t launch_xc_arrays(int xc, const double *rho, const double *sigma, int64_t n, double rho_cut, double *f,
                             double *vr, double *vs, hipStream_t s);
 // functional surrogate (mlp.hip)

@@ -475,8 +475,9 @@ __global__ __launch_bounds__(256) void k_xfunc_mlp(FArgs A, MlpDev m) {
     const Xc f = ok[j] ? mlp_output(m, rho, ys[j]) : xc_eval(A.xc, rho, sigma, A.rho_cut);
     const double wgt = A.g.w[ip];
     const int64_t o = A.g.orig[ip];
-    if (A.rho_out && o >= 0) A.rho_out[o] = rho;
-    if (A.sigma_out && o >= 0) A.sigma_out[o] = sigma;
+    double *rho_out = A.io->rho, *sigma_out = A.io->sigma;
+    if (rho_out && o >= 0) rho_out[o] = rho;
+    if (sigma_out && o >= 0) sigma_out[o] = sigma;
     double *cf = A.coef + size_t(ip) * 4;
     cf[0] = 0.5 * wgt * f.vr;
     cf[1] = 2.0 * wgt * f.vs * gs[0][j];

@@ -310,6 +310,7 @@ kldi_status kldi_plan_attach_mlp(kldi_plan *plan, const kldi_mlp *M) {
   }
   plan->impl.has_mlp = M != nullptr;
   if (M) plan->impl.mlp = view(*M);
+  kldi::invalidate_graphs(plan->impl);
   return KLDI_OK;
 }
 

@@ -18,6 +18,10 @@ Recipes (one per workload; seeds: geometry 1000+k, basis 2000+k, orbitals 3000+k
    blocks; 400 occupied orbitals; PBE.
 2  1000-atom globular cluster (500 heavy / 500 light, uniform in a sphere at 0.1 atoms/A^3, min
    separation 1.0 A); grid 75 x 302; 256-point blocks; 2000 occupied orbitals; PBE.
+3  batch of 256 independent molecules: atom counts U{5..60} drawn from rng(4003); molecule j is
+   built by the recipe of 0 with round(n/3) heavy atoms in a cube of side 8 A (n/12)^(1/3) (the
+   atom density of 0), grid 50 x 194, round(N_AO/10) occupied orbitals, seeds (1000000+j,
+   2000000+j, 3000000+j); the Becke partition keeps the atoms within 8 bohr as for 1, 2 and 4.
 4  500-atom cluster by the recipe of 2; 1000 occupied orbitals.
 Workloads 1, 2 and 4 keep, for each grid point, only the atoms within 8 bohr of its nearest atom in
 the Becke partition (a partition of unity over that neighbour set); workload 0 uses all atoms.
@@ -517,3 +521,56 @@ def tiny_problem(n_atoms=3, n_rad=12, n_ang=26, n_occ=3, xc="lda", seed=7, heavy
     recipe = dict(kind="cube", n_heavy=n_heavy, n_light=n_atoms - n_heavy, box_A=box_A, n_rad=n_rad,
                   n_ang=n_ang, G=G, n_occ=n_occ, xc=xc, min_sep_A=0.9)
     return build_problem(recipe, (seed, seed + 1, seed + 2), name="tiny%d" % seed)
+
+
+# --------------------------------------------------------------------------------------------
+# batches of independent molecules
+# --------------------------------------------------------------------------------------------
+BATCH_RECIPE = dict(n_mol=256, atoms=(5, 60), n_rad=50, n_ang=194, G=128, becke_cutoff=8.0, seed=4003)
+
+
+def batch_member(n_atoms, j, n_rad=50, n_ang=194, xc="lda", becke_cutoff=8.0):
+    """Molecule j of a batch: the recipe of workload 0 scaled to n_atoms at the same atom density."""
+    n_heavy = int(round(n_atoms / 3.0))
+    box = 8.0 * (n_atoms / 12.0) ** (1.0 / 3.0)
+    g_rng = np.random.default_rng(1000000 + j)
+    xyz, heavy = cube_molecule(g_rng, n_heavy, n_atoms - n_heavy, box)
+    basis = make_basis(np.random.default_rng(2000000 + j), heavy)
+    grid = make_grid(xyz, n_rad, n_ang, becke_cutoff)
+    S = overlap_matrix(basis, xyz)
+    n_occ = max(1, int(round(basis.n_ao / 10.0)))
+    D = make_density(np.random.default_rng(3000000 + j), S, n_occ)
+    return Problem(name="mol%d" % j, atom_xyz=xyz, atom_heavy=heavy, basis=basis, grid=grid, D=D, n_occ=n_occ,
+                   xc=xc, grid_block=128,
+                   meta=dict(recipe=dict(kind="cube", n_heavy=n_heavy, n_light=n_atoms - n_heavy, box_A=box,
+                                         n_rad=n_rad, n_ang=n_ang, becke_cutoff=becke_cutoff),
+                             seeds=[1000000 + j, 2000000 + j, 3000000 + j], generator=GENERATOR_VERSION))
+
+
+def batch_sizes(n_mol=256, atoms=(5, 60), seed=4003):
+    """Atom counts of the molecules of a batch, U{atoms[0]..atoms[1]}."""
+    return np.random.default_rng(seed).integers(atoms[0], atoms[1] + 1, size=n_mol)
+
+
+def make_batch(n_mol=None, atoms=None, n_rad=None, n_ang=None, xc="lda", cache=True):
+    """The molecules of the batching workload (defaults: BATCH_RECIPE); the first n_mol of them if
+    n_mol is smaller than 256 (sizes always come from the same draw)."""
+    r = dict(BATCH_RECIPE)
+    for k, v in (("n_mol", n_mol), ("atoms", atoms), ("n_rad", n_rad), ("n_ang", n_ang)):
+        if v is not None:
+            r[k] = v
+    sizes = batch_sizes(max(r["n_mol"], 1), r["atoms"], r["seed"])[: r["n_mol"]]
+    out = []
+    for j, n in enumerate(sizes):
+        key = hashlib.sha1(repr((GENERATOR_VERSION, int(n), j, r["n_rad"], r["n_ang"], r["becke_cutoff"])).encode()
+                           ).hexdigest()[:16]
+        path = os.path.join(_cache_dir(), "batch_%s.npz" % key)
+        if cache and os.path.exists(path):
+            p = _load(path, {})
+            p.xc = xc
+        else:
+            p = batch_member(int(n), j, r["n_rad"], r["n_ang"], xc, r["becke_cutoff"])
+            if cache:
+                _save(p, path)
+        out.append(p)
+    return out

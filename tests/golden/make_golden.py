@@ -1,9 +1,12 @@
 """Writes the stored expected values of the full-size parity tests.
 
-Calls only the seeded input generator and the FP64 oracle (never the HIP library):
-  cfg1_oracle.json  200-atom chain, PBE: dense E_xc, the electron count, rho and grad rho at 2000
-                    seeded random points, and 4000 seeded random entries of Vxc (plus its diagonal).
-Run from the repository root:  python tests/golden/make_golden.py
+Calls only the seeded input generator and the FP64 oracle (never the HIP library).  Both files hold the
+same seeded samples: 2000 random grid points and 4000 random (mu, nu) entries of Vxc (plus its
+diagonal), drawn from numpy's default_rng(12345).
+  cfg1_oracle.json   200-atom chain, PBE: dense (unscreened) evaluation, oracle.eval_exc
+  cfg1_blocked.json  the same problem with the block filter at t_b = t_d = 1e-10, d = 32, G = 128,
+                     oracle.blocked.eval_blocked_stream (the method's own result at those thresholds)
+Run from the repository root:  python tests/golden/make_golden.py [dense|blocked]
 """
 import json
 import os
@@ -19,17 +22,20 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 
-def main():
-    k = 1
-    p = synth.make_problem(k)
-    t0 = time.time()
-    r = oracle.eval_exc(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.D, p.xc, chunk=4096)
-    dt = time.time() - t0
+def samples(p):
     rng = np.random.default_rng(12345)
     pts = np.sort(rng.choice(p.n_points, 2000, replace=False))
     ij = rng.integers(0, p.n_ao, size=(4000, 2))
+    return pts, ij
+
+
+def dense(p):
+    t0 = time.time()
+    r = oracle.eval_exc(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.D, p.xc, chunk=4096)
+    dt = time.time() - t0
+    pts, ij = samples(p)
     V = r["V"]
-    out = {
+    return {
         "workload": "cfg1: 200-atom chain, 2000 AOs, 4.53M points, PBE, dense (unscreened) FP64 oracle",
         "generator": synth.GENERATOR_VERSION, "seeds": p.meta["seeds"], "oracle_seconds": dt,
         "E": r["E"], "electrons": float(p.grid.weight @ r["rho"]), "n_occ": p.n_occ,
@@ -37,10 +43,42 @@ def main():
         "v_ij": ij.tolist(), "v": V[ij[:, 0], ij[:, 1]].tolist(), "v_diag": np.diag(V).tolist(),
         "v_maxabs": float(np.abs(V).max()), "v_asym": float(np.abs(V - V.T).max()),
     }
-    path = os.path.join(ROOT, "tests", "golden", "cfg1_oracle.json")
-    with open(path, "w") as f:
-        json.dump(out, f)
-    print("wrote", path, "E =", r["E"], "in %.0f s" % dt)
+
+
+def blocked(p, t=1e-10):
+    pts, ij = samples(p)
+    diag = np.stack([np.arange(p.n_ao)] * 2, 1)
+    t0 = time.time()
+
+    def prog(done, tot):
+        if done % (32 * 100) == 0 or done == tot:
+            print("  %d / %d blocks, %.0f s" % (done, tot, time.time() - t0), flush=True)
+
+    r = oracle.blocked.eval_blocked_stream(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom,
+                                           p.D, p.xc, t_b=t, t_d=t, d_ao=32, G=128,
+                                           v_entries=np.concatenate([ij, diag]), progress=prog)
+    dt = time.time() - t0
+    v = r["v"]
+    return {
+        "workload": "cfg1: 200-atom chain, 2000 AOs, 4.53M points, PBE, block-filtered FP64 oracle "
+                    "(t_b = t_d = %g, d = 32, G = 128)" % t,
+        "t_b": t, "t_d": t, "generator": synth.GENERATOR_VERSION, "seeds": p.meta["seeds"], "oracle_seconds": dt,
+        "E": r["E"], "electrons": float(p.grid.weight @ r["rho"]), "n_occ": p.n_occ,
+        "n_pairs_x": r["nP_X"], "n_pairs_v": r["nP_M"],
+        "rho_idx": pts.tolist(), "rho": r["rho"][pts].tolist(),
+        "v_ij": ij.tolist(), "v": v[:len(ij)].tolist(), "v_diag": v[len(ij):].tolist(),
+    }
+
+
+def main():
+    which = sys.argv[1:] or ["dense", "blocked"]
+    p = synth.make_problem(1)
+    for w in which:
+        out = dense(p) if w == "dense" else blocked(p)
+        path = os.path.join(ROOT, "tests", "golden", "cfg1_oracle.json" if w == "dense" else "cfg1_blocked.json")
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print("wrote", path, "E =", out["E"], "in %.0f s" % out["oracle_seconds"], flush=True)
 
 
 if __name__ == "__main__":

@@ -37,11 +37,12 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_version_and_defaults(L):
-    assert L.kldi_version() == 1
+    assert L.kldi_version() == 2
     o = L.kldi_opts()
     L.kldi_opts_default(ctypes.byref(o))
     assert o.t_b == 1e-10 and o.t_d == 1e-10 and o.rho_cut == 1e-14
     assert o.grid_block == 128 and o.ao_block == 32 and o.prec == 0 and o.xc == 1
+    assert o.v_segment == 0 and o.chunk_tiles == 0 and o.schedule == 0
 
 
 def _structs(L, p, **kw):
@@ -69,7 +70,7 @@ def _create(L, b, g, o):
 
 @pytest.mark.parametrize("bad", ["null_basis", "null_grid", "null_opts", "neg_tb", "nan_td", "bad_l", "bad_ptr",
                                  "neg_exp", "bad_atom", "bad_point_atom", "zero_points", "block_not_64",
-                                 "bad_prec", "bad_xc", "nan_xyz"])
+                                 "bad_prec", "bad_xc", "nan_xyz", "bad_schedule", "neg_segment"])
 def test_invalid_arguments_rejected_before_any_launch(L, bad):
     p = synth.tiny_problem(seed=2)
     b, g, o, keep = _structs(L, p)
@@ -103,6 +104,10 @@ def test_invalid_arguments_rejected_before_any_launch(L, bad):
         o.xc = 42
     elif bad == "nan_xyz":
         keep[6][5, 1] = float("nan")
+    elif bad == "bad_schedule":
+        o.schedule = 5
+    elif bad == "neg_segment":
+        o.v_segment = -2
     st, h = _create(L, b, g, o)
     assert st == -1, (bad, st, L.kldi_last_error())
     assert h.value is None
@@ -124,3 +129,28 @@ def test_null_handles(L):
     assert L.kldi_plan_info(None, None) == -1
     assert L.kldi_eval_check(None, None, None) == -1
     assert L.kldi_plan_structure(None, None, None, None, None) == -1
+
+
+def test_batch_arguments_rejected_before_any_launch(L):
+    """kldi_batch_create validates every molecule (and n_mol) before touching the device."""
+    ps = [synth.tiny_problem(seed=2), synth.tiny_problem(n_atoms=2, seed=3)]
+    parts = [_structs(L, p) for p in ps]
+    o = parts[0][2]
+    B = (L.kldi_basis * 2)(parts[0][0], parts[1][0])
+    G = (L.kldi_grid * 2)(parts[0][1], parts[1][1])
+    h = ctypes.c_void_p(123)
+    assert L.kldi_batch_create(0, B, G, ctypes.byref(o), None, ctypes.byref(h)) == -1
+    assert h.value is None
+    parts[1][3][8][0] = 7                       # molecule 1: a point of a missing atom
+    G = (L.kldi_grid * 2)(parts[0][1], parts[1][1])
+    h = ctypes.c_void_p(123)
+    assert L.kldi_batch_create(2, B, G, ctypes.byref(o), None, ctypes.byref(h)) == -1
+    assert h.value is None
+    assert b"molecule 1" in L.kldi_last_error()
+    assert L.kldi_batch_create(2, None, G, ctypes.byref(o), None, ctypes.byref(h)) == -1
+
+
+def test_null_handles_of_batch_graph_and_tuning(L):
+    assert L.kldi_batch_layout(None, None, None, None) == -1
+    assert L.kldi_plan_graph(None, 1) == -1
+    assert L.kldi_plan_autotune(None, None, 1, None, None) == -1

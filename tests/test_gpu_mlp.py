@@ -24,13 +24,19 @@ def test_xc_eval_arrays_match_oracle(mod):
     rng = np.random.default_rng(3)
     rho = 10 ** rng.uniform(-12, 2, 5000)
     sig = rho ** (8 / 3) * 10 ** rng.uniform(-4, 2, 5000)
+    # PBE's mu = beta pi^2 / 3 makes the gradient terms of exchange and correlation cancel to leading
+    # order in s, so v_sigma of "pbe" is a small difference of two larger parts: its rounding error is
+    # bounded relative to |v_sigma,x| + |v_sigma,c|, not to |v_sigma|
+    vs_scale = np.abs(fx.pbe_x(rho, sig)[2]) + np.abs(fx.pbe_c(rho, sig)[2])
     for xc in ("lda", "pbe", "pbe_x"):
         f, vr, vs = mod.xc_eval(xc, torch.from_numpy(rho).cuda(), torch.from_numpy(sig).cuda(), 1e-14)
         ef, evr, evs = fx.evaluate(xc, rho, sig, 1e-14)
         assert np.allclose(f.cpu().numpy(), ef, rtol=1e-12, atol=0)
         assert np.allclose(vr.cpu().numpy(), evr, rtol=1e-12, atol=0)
         if xc != "lda":
-            assert np.allclose(vs.cpu().numpy(), evs, rtol=1e-11, atol=0)
+            dvs = np.abs(vs.cpu().numpy() - evs)
+            print("%s: max |dv_sigma| / (|v_sigma,x| + |v_sigma,c|) = %.2e" % (xc, (dvs / vs_scale).max()))
+            assert np.all(dvs <= 1e-12 * vs_scale)
 
 
 def test_eval_grid_rho_and_sigma(mod):

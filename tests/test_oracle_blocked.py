@@ -103,3 +103,24 @@ def test_error_grows_with_pair_threshold():
     assert all(x >= y for x, y in zip(pairs, pairs[1:]))
     assert pairs[-1] < pairs[0]
     assert errs[-1] > errs[0]
+
+
+# ---------------------------------------------------------------- block-at-a-time evaluation
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+@pytest.mark.parametrize("t", [1e-10, 1e-6])
+def test_stream_evaluation_equals_blocked(xc, t):
+    """eval_blocked_stream visits the grid blocks one at a time; it must reproduce eval_blocked (the
+    same executed pairs, the same E, rho and V up to rounding) and its sampled V entries must be the
+    entries of its full V."""
+    p = synth.tiny_problem(n_atoms=5, n_rad=16, n_ang=38, n_occ=5, xc=xc, seed=71, box_A=5.0)
+    args = (p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc)
+    ref = oracle.eval_blocked(*args, t_b=t, t_d=t)
+    s = oracle.blocked.eval_blocked_stream(*args, t_b=t, t_d=t, blocks_per_chunk=3)
+    assert (s["nP_X"], s["nP_M"]) == (ref["nP_X"], ref["nP_M"])
+    assert abs(s["E"] - ref["E"]) <= 1e-13 * abs(ref["E"])
+    assert np.abs(s["rho"] - ref["rho"]).max() <= 1e-13 * np.abs(ref["rho"]).max()
+    assert np.abs(s["V"] - ref["V"]).max() <= 1e-13 * np.abs(ref["V"]).max()
+    ij = np.random.default_rng(1).integers(0, p.n_ao, size=(300, 2))
+    ij = np.concatenate([ij, np.stack([np.arange(p.n_ao)] * 2, 1)])
+    v = oracle.blocked.eval_blocked_stream(*args, t_b=t, t_d=t, blocks_per_chunk=2, v_entries=ij)["v"]
+    assert np.abs(v - s["V"][ij[:, 0], ij[:, 1]]).max() <= 1e-13 * np.abs(ref["V"]).max()
