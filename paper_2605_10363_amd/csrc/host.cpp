@@ -539,7 +539,7 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
 
   // grid chunks: whole segments whose retained tiles fit the Phi / Z workspaces
   const size_t esz = (P.opts.prec == KLDI_PREC_FP64) ? 8 : 4;
-  const size_t per_tile = 2 * 4096 * esz;       // Phi + Z
+  const size_t per_tile = 2 * 4096 * esz + (esz == 4 ? 4096 * 2 : 0);   // Phi + Z (+ bf16 low part of Phi)
   const size_t vfixed = P.items_h.size() * (16384 * 8 + 4);
   int64_t cap = chunk_tiles;
   {
@@ -573,6 +573,17 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
 
   // queues of the persistent schedule, per grid chunk
   const size_t nch = P.chunks_h.size();
+  {
+    // Vxc items of diagonal chunk pairs, per grid chunk (their diagonal tiles run in FP64)
+    std::vector<int> di;
+    P.dchunk_h.assign(nch + 1, 0);
+    for (size_t ci = 0; ci < nch; ++ci) {
+      for (int64_t it = P.chunks_h[ci].vit0; it < P.chunks_h[ci].vit1; ++it)
+        if (P.items_h[it].pc == P.items_h[it].qc) di.push_back(int(it));
+      P.dchunk_h[ci + 1] = int64_t(di.size());
+    }
+    P.ditems = dev_upload(P, di, true);
+  }
   {
     std::vector<int> xorder, vorder;
     std::vector<int64_t> xqoff(9 * nch), vqoff(9 * nch);
@@ -613,9 +624,11 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
   if (esz == 8) {
     E.phi = dev_alloc<double>(P, size_t(max_ret) * 4096, true);
     E.zws = dev_alloc<double>(P, size_t(max_ret) * 4096, true);
+    E.phil = nullptr;
   } else {
     E.phi = dev_alloc<float>(P, size_t(max_ret) * 4096, true);
     E.zws = dev_alloc<float>(P, size_t(max_ret) * 4096, true);
+    E.phil = dev_alloc<unsigned short>(P, size_t(max_ret) * 4096, true);
   }
   E.xpart = dev_alloc<double>(P, size_t(max_xit) * 4 * kG, true);
   E.vpart = dev_alloc<double>(P, P.items_h.size() * 16384, true);

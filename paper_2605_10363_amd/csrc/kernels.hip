@@ -24,6 +24,8 @@
 // from per-XCD queues (kldi_schedule).
 #include <algorithm>
 
+#include <hip/hip_bf16.h>
+
 #include "device.h"
 
 namespace kldi {
@@ -74,6 +76,16 @@ __global__ __launch_bounds__(NT) void k_begin(IoDev *cell, IoDev io, unsigned lo
   for (int i = threadIdx.x; i < nq; i += NT) qcnt[i] = 0;
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+  __hip_bfloat16 b = __float2bfloat16(x);
+  return *reinterpret_cast<unsigned short *>(&b);
+}
+__device__ __forceinline__ double from_bf16(unsigned short u) {
+  return double(__uint_as_float(uint32_t(u) << 16));
+}
+
 // Molecule m with off(mol[m]) <= x < off(mol[m + 1]) for an increasing offset field.
 template <class F>
 __device__ __forceinline__ int find_mol(const MolDev *mol, int n_mol, int64_t x, F &&off) {
@@ -114,15 +126,29 @@ __global__ __launch_bounds__(NT) void k_dprep(const MolDev *__restrict__ mol, in
   if (threadIdx.x == 0) amax[g] = fmax(fmax(s[0], s[1]), fmax(s[2], s[3]));
 }
 
+// FP32 operands also get Phi_lo = bf16(Phi - fl32(Phi)) (phil != NULL): the term the split product of
+// the Vxc GEMM adds back.
 template <class T>
-__global__ __launch_bounds__(kG) void k_basis(BasisDev B, GridDev g, StructDev st, int64_t ret0, T *__restrict__ phi) {
+__global__ __launch_bounds__(kG) void k_basis(BasisDev B, GridDev g, StructDev st, int64_t ret0, T *__restrict__ phi,
+                                             unsigned short *__restrict__ phil) {
   const int64_t k = ret0 + blockIdx.x;     // retained tile; the workspace holds the chunk from ret0
   const int p = st.ret_p[k];
   const int64_t ip = int64_t(st.ret_r[k]) * kG + threadIdx.x;
   const double x = g.x[ip], y = g.y[ip], z = g.z[ip];
-  T *out = phi + size_t(blockIdx.x) * (kD * kG) + threadIdx.x;
+  const size_t o = size_t(blockIdx.x) * (kD * kG) + threadIdx.x;
+  T *out = phi + o;
   for (int a = B.tile_nv[p]; a < kD; ++a) out[a * kG] = T(0);
-  for_tile_aos<false>(B, p, x, y, z, [&](int a, double v, double, double, double) { out[a * kG] = T(v); });
+  if (sizeof(T) == 4 && phil) {
+    unsigned short *lo = phil + o;
+    for (int a = B.tile_nv[p]; a < kD; ++a) lo[a * kG] = 0;
+    for_tile_aos<false>(B, p, x, y, z, [&](int a, double v, double, double, double) {
+      const T h = T(v);
+      out[a * kG] = h;
+      lo[a * kG] = to_bf16(float(v - double(h)));
+    });
+  } else {
+    for_tile_aos<false>(B, p, x, y, z, [&](int a, double v, double, double, double) { out[a * kG] = T(v); });
+  }
 }
 
 // 16-byte unit copies between global memory and LDS rows
@@ -181,6 +207,7 @@ struct XArgs {
   const void *Dt;
   const double *amax;
   const void *phi;
+  const unsigned short *phil;   // FP32 operands: bf16(Phi - fl32(Phi)), else NULL
   double *part;            // [n_items][4][kG] rho, grad rho partial sums, indexed from item0
   unsigned long long *counters;
   double t_b, t_d;
@@ -402,7 +429,12 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
         });
       } else {
         const T *ph = phi + size_t(k0 + slot) * (kD * kG) + j;
-        for (int a = 0; a < kD; ++a) s0 += double(ph[a * kG]) * Xw[a * kG + j];
+        if (sizeof(T) == 4 && A.phil) {
+          const unsigned short *pl = A.phil + size_t(k0 + slot - A.ret0) * (kD * kG) + j;
+          for (int a = 0; a < kD; ++a) s0 += (double(ph[a * kG]) + from_bf16(pl[a * kG])) * Xw[a * kG + j];
+        } else {
+          for (int a = 0; a < kD; ++a) s0 += double(ph[a * kG]) * Xw[a * kG + j];
+        }
       }
       s_acc[slot_h][0][j] += s0;
       s_acc[slot_h][1][j] += 2.0 * sx;
@@ -464,29 +496,35 @@ __global__ __launch_bounds__(kG) void k_xfunc(FArgs A) {
 template <class T, bool GGA>
 __global__ __launch_bounds__(kG) void k_zform(BasisDev B, GridDev g, StructDev st, int64_t ret0,
                                              const double *__restrict__ coef, const T *__restrict__ phi,
-                                             T *__restrict__ zws, double *__restrict__ zmax) {
+                                             const unsigned short *__restrict__ phil, T *__restrict__ zws,
+                                             double *__restrict__ zmax) {
   const int64_t k = ret0 + blockIdx.x;
   const int j = threadIdx.x;
   const int p = st.ret_p[k];
   const int64_t ip = int64_t(st.ret_r[k]) * kG + j;
   const double *cf = coef + size_t(ip) * 4;
   const double c0 = cf[0];
-  T *out = zws + size_t(blockIdx.x) * (kD * kG) + j;
+  const size_t o = size_t(blockIdx.x) * (kD * kG) + j;
+  T *out = zws + o;
   double zm = 0.0;
+  auto put = [&](int a, double zv) {
+    const T zt = T(zv);
+    out[a * kG] = zt;
+    zm = fmax(zm, fabs(double(zt)));
+  };
   if (GGA) {
     const double c1x = cf[1], c1y = cf[2], c1z = cf[3];
     for (int a = B.tile_nv[p]; a < kD; ++a) out[a * kG] = T(0);
     for_tile_aos<true>(B, p, g.x[ip], g.y[ip], g.z[ip], [&](int a, double v, double gx, double gy, double gz) {
-      const T zt = T(c0 * v + c1x * gx + c1y * gy + c1z * gz);
-      out[a * kG] = zt;
-      zm = fmax(zm, fabs(double(zt)));
+      put(a, c0 * v + c1x * gx + c1y * gy + c1z * gz);
     });
   } else {
-    const T *in = phi + size_t(blockIdx.x) * (kD * kG) + j;
+    // Z from the stored Phi, with its low part for FP32 operands (Z then carries no rounding of Phi)
+    const T *in = phi + o;
     for (int a = 0; a < kD; ++a) {
-      const T zt = T(c0 * double(in[a * kG]));
-      out[a * kG] = zt;
-      zm = fmax(zm, fabs(double(zt)));
+      double v = double(in[a * kG]);
+      if (sizeof(T) == 4 && phil) v += from_bf16(phil[o + a * kG]);
+      put(a, c0 * v);
     }
   }
   __shared__ double s[2];
@@ -568,6 +606,7 @@ struct VArgs {
   QArgs q;
 };
 
+
 constexpr int NTV = 512;   // threads per Vxc workgroup: 8 waves, each 32 rows x 64 columns
 
 // One workgroup per (row chunk pc, column chunk qc, segment of grid blocks): M_pq = sum_r Phi_pr Z_qr^T
@@ -579,6 +618,11 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
   constexpr int kS = 128 * LDA_S;  // one A or B stage (4 tiles x 32 rows x 32 points)
+  // FP32 operands: M = Phi Z^T on FP32 MFMA, accumulators flushed to FP64 after every slab.  The
+  // diagonal tiles p = q are left to k_vdiag (FP64): they hold the large same-sign sums w v Phi_mu^2
+  // whose FP32 rounding, correlated over the points of one radial shell where Phi takes one value,
+  // would dominate the error of the mixed path.
+  constexpr bool SPLIT = sizeof(T) == 4;
   __shared__ __align__(16) T sA[2 * kS];
   __shared__ __align__(16) T sB[2 * kS];
   __shared__ int s_m[NTV];
@@ -605,6 +649,8 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
     }
   unsigned long long pairs = 0;
   int any = 0;
+  // column tile (0 or 1 of this wave's two) that is the diagonal tile p = q, or -1
+  const int dcol = (SPLIT && it.pc == it.qc && (u >> 1) == h) ? (u & 1) : -1;
 
   for (int base = it.r0; base < it.r1; base += NTV) {
     const int r = base + tid;
@@ -681,6 +727,8 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
       if (wm) {
         const T *a = sA + buf * kS;
         const T *b = sB + buf * kS;
+        // FP32 tiles (all but the diagonal one)
+        const int wf = (SPLIT && dcol >= 0) ? (wm & ~(1 << dcol)) : wm;
 #pragma unroll 2
         for (int kk = 0; kk < 8; ++kk) {
           const int kc = 4 * kk + (l >> 4);
@@ -688,7 +736,7 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
           const T a1 = a[(32 * u + 16 + (l & 15)) * LDA_S + kc];
 #pragma unroll
           for (int tj = 0; tj < 4; ++tj) {
-            if ((wm >> (tj >> 1)) & 1) {
+            if ((wf >> (tj >> 1)) & 1) {
               const T bv = b[(64 * h + 16 * tj + (l & 15)) * LDA_S + kc];
               acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
               acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
@@ -722,12 +770,14 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
+    for (int tj = 0; tj < 4; ++tj) {
+      if ((tj >> 1) == dcol) continue;        // written by k_vdiag
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 32 * u + 16 * ti + M::row(v, l), col = 64 * h + 16 * tj + (l & 15);
         out[row * 128 + col] = dacc[ti][tj][v] + double(acc[ti][tj][v]);
       }
+    }
   if (tid == 0) A.vflag[item] = 1;
   double pd = wave_sum(double(pairs));
   if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
@@ -735,6 +785,69 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
 }
 
 // One workgroup row per chunk pair (all molecules): FP64 sum of its segment partials in segment order.
+// FP32 plans: the diagonal tiles M_pp of the Vxc product in FP64.  One workgroup per Vxc item of a
+// diagonal chunk pair (pc = qc); wave w owns the tile p = 4 pc + w and walks the segment's blocks whose
+// pair mask executes (p, p) (eq. block_pair_filter, as k_vgemm), M_pp += Phi_pr Z_pr^T on FP64 MFMA with
+// the operand Phi_hi + Phi_lo; the result goes to the tile's place in the item's partial, which
+// k_vgemm wrote for every other tile.
+struct VDArgs {
+  StructDev st;
+  const VItem *items;
+  const int *ditems;       // items of diagonal chunk pairs, this launch
+  int64_t n;
+  int64_t ret0;
+  const int *cinfo;
+  const int64_t *cioff, *vmoff;
+  int64_t vm_base;
+  const unsigned short *vmask;
+  const float *phi;
+  const unsigned short *phil;
+  const float *zws;
+  const int *vflag;
+  double *vpart;
+};
+
+__global__ __launch_bounds__(NT) void k_vdiag(VDArgs A) {
+  const int64_t item = A.ditems[blockIdx.x];
+  if (!A.vflag[item]) return;     // nothing executed in this item: k_vgemm wrote no partial
+  const VItem it = A.items[item];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  d4 dd[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti) dd[ti][0] = dd[ti][1] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int r = it.r0; r < it.r1; ++r) {
+    const int mask = A.vmask[A.vmoff[r] - A.vm_base + it.lpair];
+    if (!((mask >> (5 * w)) & 1)) continue;      // bit 4 w + w: the pair (p, p)
+    const int ci = A.cinfo[A.cioff[r] + it.pc];
+    const size_t t = size_t(A.st.blk_off[r] + tile_pos(ci, w) - A.ret0) * (kD * kG);
+    const float *ph = A.phi + t;
+    const unsigned short *pl = A.phil + t;
+    const float *zt = A.zws + t;
+    const int i0 = l & 15;
+    for (int kk = 0; kk < kG / 4; ++kk) {
+      const int kc = 4 * kk + (l >> 4);
+      const double a0 = double(ph[i0 * kG + kc]) + from_bf16(pl[i0 * kG + kc]);
+      const double a1 = double(ph[(i0 + 16) * kG + kc]) + from_bf16(pl[(i0 + 16) * kG + kc]);
+      const double b0 = double(zt[i0 * kG + kc]);
+      const double b1 = double(zt[(i0 + 16) * kG + kc]);
+      dd[0][0] = Mma<double>::mma(a0, b0, dd[0][0]);
+      dd[0][1] = Mma<double>::mma(a0, b1, dd[0][1]);
+      dd[1][0] = Mma<double>::mma(a1, b0, dd[1][0]);
+      dd[1][1] = Mma<double>::mma(a1, b1, dd[1][1]);
+    }
+  }
+  double *out = A.vpart + size_t(item) * (128 * 128);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 32 * w + 16 * ti + Mma<double>::row(v, l), col = 32 * w + 16 * tj + (l & 15);
+        out[row * 128 + col] = dd[ti][tj][v];
+      }
+}
+
 __global__ __launch_bounds__(NT) void k_vreduce(const int *pair_ptr, const int *pair_items, const int *pair_info,
                                                const MolDev *mol, const int *__restrict__ vflag,
                                                const double *__restrict__ vpart, double *__restrict__ mfull) {
@@ -817,7 +930,7 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
   for (size_t ci = 0; ci < P.chunks_h.size(); ++ci) {
     const GridChunk &C = P.chunks_h[ci];
     const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nxit = C.xit1 - C.xit0, nvit = C.vit1 - C.vit0;
-    if (nret > 0) k_basis<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, static_cast<T *>(E.phi));
+    if (nret > 0) k_basis<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, static_cast<T *>(E.phi), E.phil);
     if (one) mark(2);
     XArgs xa;
     xa.B = P.basis;
@@ -831,6 +944,7 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
     xa.Dt = E.Dt;
     xa.amax = E.amax;
     xa.phi = E.phi;
+    xa.phil = E.phil;
     xa.part = E.xpart;
     xa.counters = E.counters;
     xa.t_b = P.opts.t_b;
@@ -870,10 +984,10 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
     if (want_v && nret > 0) {
       if (P.gga)
         k_zform<T, true><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, static_cast<const T *>(E.phi),
-                                             static_cast<T *>(E.zws), E.zmax);
+                                             E.phil, static_cast<T *>(E.zws), E.zmax);
       else
         k_zform<T, false><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, static_cast<const T *>(E.phi),
-                                              static_cast<T *>(E.zws), E.zmax);
+                                              E.phil, static_cast<T *>(E.zws), E.zmax);
     }
     if (one) mark(4);
     if (want_v && nblk > 0) {
@@ -914,6 +1028,26 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
         gv = persistent_grid(occ_v, P.n_cu, nvit);
       }
       if (nvit > 0) k_vgemm<T><<<gv, NTV, 0, s>>>(va);
+      const int64_t nd = P.dchunk_h[ci + 1] - P.dchunk_h[ci];
+      if (sizeof(T) == 4 && nd > 0) {
+        VDArgs da;
+        da.st = P.st;
+        da.items = P.items;
+        da.ditems = P.ditems + P.dchunk_h[ci];
+        da.n = nd;
+        da.ret0 = C.ret0;
+        da.cinfo = P.cinfo;
+        da.cioff = P.cioff;
+        da.vmoff = P.vmoff;
+        da.vm_base = P.vmoff_h[C.blk0];
+        da.vmask = E.vmask;
+        da.phi = static_cast<const float *>(E.phi);
+        da.phil = E.phil;
+        da.zws = static_cast<const float *>(E.zws);
+        da.vflag = E.vflag;
+        da.vpart = E.vpart;
+        k_vdiag<<<nd, NT, 0, s>>>(da);
+      }
     }
   }
   mark(5);

@@ -91,6 +91,7 @@ struct EvalDev {
   double *amax;            // [sum nt^2] max |D_pq|
   void *phi;               // [max chunk retained tiles * 4096] Phi workspace, working precision
   void *zws;               // [max chunk retained tiles * 4096] Z workspace
+  unsigned short *phil;    // FP32 plans: [max chunk retained tiles * 4096] bf16(Phi - fl32(Phi)); else NULL
   double *xpart;           // [max chunk X items * 4 * 128] rho / grad rho partials of each X work item
   double *coef;            // [n_pad * 4] Z coefficients per point
   double *zmax;            // [n_ret]
@@ -176,6 +177,8 @@ struct Plan {
   int64_t *vmoff = nullptr;  // [n_blocks+1] first vmask entry of each block
   int32_t *ao_perm_d = nullptr;
   Queues xq, vq;
+  int *ditems = nullptr;              // Vxc items of diagonal chunk pairs (pc = qc), grouped by grid chunk
+  std::vector<int64_t> dchunk_h;      // [n_gchunks + 1] offsets into ditems
   // functional surrogate attached with kldi_plan_attach_mlp
   bool has_mlp = false;
   MlpDev mlp{};
