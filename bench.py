@@ -166,13 +166,99 @@ def bench_batch(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args, torch):
+    """The learned form: a 2-64-64-64-3 SiLU network trained on the GPU on (rho, sigma) points of the
+    200-atom chain and the 1000-atom cluster stands in for PBE on the 500-atom cluster."""
+    import synth
+    from paper_2605_10363_amd.plan import Plan, Mlp
+    from oracle import functionals as fx
+    t0 = time.time()
+    rs, ss = [], []
+    for k, n_take in ((1, 4_530_000), (2, 5_470_000)):
+        p = synth.make_problem(k)
+        plan = Plan.from_problem(p, prec="fp32")
+        r, s = plan.eval_grid(torch.from_numpy(p.D).cuda())
+        g = torch.Generator(device="cpu").manual_seed(5000 + k)
+        idx = torch.randperm(p.n_points, generator=g)[:n_take].cuda()
+        rs.append(r[idx])
+        ss.append(s[idx])
+        plan.close()
+        del r, s
+        torch.cuda.empty_cache()
+        log("training points from %s: %d of %d (%.1f s)" % (p.name, n_take, p.n_points, time.time() - t0))
+    rho_t, sig_t = torch.cat(rs), torch.cat(ss)
+    n_train = int(rho_t.numel())
+    net = Mlp(seed=7)
+    t1 = time.time()
+    losses = net.train(rho_t, sig_t, epochs=args.epochs, batch=16384, lr=2e-3, seed=11, xc="pbe", rho_min=1e-8)
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    log("trained %d epochs on %d points in %.1f s; loss %s" % (args.epochs, rho_t.numel(), train_s,
+                                                               np.array2string(losses[::max(1, len(losses) // 5)], precision=4)))
+    # inference against the analytic functional (and the oracle's functional) on training-range samples
+    sel = torch.randperm(rho_t.numel(), generator=torch.Generator().manual_seed(3))[:200000].cuda()
+    f, vr, vs, used = net.forward(rho_t[sel], sig_t[sel])
+    r_np, s_np = rho_t[sel].cpu().numpy(), sig_t[sel].cpu().numpy()
+    ef, evr, evs = fx.evaluate("pbe", r_np, s_np, 1e-14)
+    u = used.cpu().numpy().astype(bool)
+    rel_f = np.abs(f.cpu().numpy()[u] - ef[u]) / np.abs(ef[u])
+    del rho_t, sig_t, rs, ss
+    torch.cuda.empty_cache()
+
+    p4 = synth.make_problem(4)
+    D4 = torch.from_numpy(p4.D).cuda()
+    log("inputs: %s n_atoms=%d n_ao=%d n_points=%d" % (p4.name, p4.n_atoms, p4.n_ao, p4.n_points))
+    out_runs = {}
+    for tag in ("analytic", "mlp"):
+        plan = Plan.from_problem(p4, prec="fp32", xc="pbe")
+        if tag == "mlp":
+            plan.attach_mlp(net)
+        ms, stage, st, E, V, rho = time_path(plan, D4, args.steps, args.warmup, torch)
+        out_runs[tag] = dict(ms=ms, stage=stage, st=st, E=E, V=V)
+        log("%s: %.3f ms/eval, functional stage %.3f ms, E %.10f, surrogate points %d" % (
+            tag, ms, stage["xfunc"], E, st["n_points_mlp"]))
+        plan.close()
+        del rho
+        torch.cuda.empty_cache()
+    plan = Plan.from_problem(p4, prec="fp64", xc="pbe")
+    ms64, stage64, st64, E64, V64, rho64 = time_path(plan, D4, 1, 1, torch)
+    plan.close()
+    a, m = out_runs["analytic"], out_runs["mlp"]
+    out = {
+        "metric": METRIC, "value": round(m["ms"], 4), "unit": "ms/eval", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(m["ms"], 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "500-atom cluster, 5000 cartesian AOs, %d points (75x302 per atom), 128-point blocks, "
+                               "PBE replaced by the trained network where it covers a point" % p4.n_points,
+                   "path": "mixed FP32 block GEMMs; BF16-weight MLP functional, analytic fallback"},
+        "learned": {
+            "train_points": n_train, "train_sources": "4.53M points of the 200-atom chain + 5.47M of the 1000-atom cluster",
+            "epochs": args.epochs,
+            "train_s": round(train_s, 2), "final_loss": float(losses[-1]),
+            "points_on_network": int(m["st"]["n_points_mlp"]), "fraction_on_network": m["st"]["n_points_mlp"] / p4.n_points,
+            "functional_ms": {"mlp": round(m["stage"]["xfunc"], 4), "analytic": round(a["stage"]["xfunc"], 4)},
+            "eval_ms": {"mlp": round(m["ms"], 4), "analytic": round(a["ms"], 4), "fp64_analytic": round(ms64, 4)},
+            "E_xc": {"mlp": m["E"], "analytic": a["E"], "fp64_analytic": E64},
+            "err_vs_analytic": {"E_xc": abs(m["E"] - a["E"]), "E_xc_rel": abs(m["E"] - a["E"]) / abs(a["E"]),
+                                "V_maxabs": float(np.abs(m["V"] - a["V"]).max())},
+            "err_vs_fp64": {"E_xc": abs(m["E"] - E64), "V_maxabs": float(np.abs(m["V"] - V64).max())},
+            "f_rel_err_vs_oracle_functional": {"median": float(np.median(rel_f)), "p99": float(np.quantile(rel_f, 0.99)),
+                                               "sample": "200000 training-range points"},
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1, help="1: 200-atom chain (default); 3: batch of 256 molecules")
+    ap.add_argument("--config", type=int, default=1,
+                    help="1: 200-atom chain (default); 2: 1000-atom cluster; 3: batch of 256 molecules; "
+                         "4: 500-atom cluster with the learned functional")
     ap.add_argument("--xc", default="lda", help="functional of the batch workload (lda or pbe)")
+    ap.add_argument("--epochs", type=int, default=10, help="training epochs of the learned form (--config 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--v-segment", type=int, default=0, help="grid blocks per Vxc segment (0 = plan's choice)")
@@ -189,6 +275,9 @@ def main():
 
     if args.config == 3:
         bench_batch(args, torch)
+        return
+    if args.config == 4:
+        bench_learned(args, torch)
         return
 
     t0 = time.time()
