@@ -238,6 +238,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
   constexpr int STAGES = (sizeof(T) == 4) ? 2 : 1;   // LDS stages of the K loop
+  constexpr int LDA_S = lda_s<T>(), LDB_S = ldb_s<T>();
   constexpr int kA = 128 * LDA_S, kB = 32 * LDB_S;
   constexpr int kStageBytes = STAGES * (kA + kB) * int(sizeof(T));
   static_assert(kStageBytes >= 2 * kD * kG * 8, "two FP64 X tiles must fit the staging area");
@@ -617,6 +618,7 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   typedef Mma<T> M;
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
+  constexpr int LDA_S = lda_s<T>();
   constexpr int kS = 128 * LDA_S;  // one A or B stage (4 tiles x 32 rows x 32 points)
   // FP32 operands: M = Phi Z^T on FP32 MFMA, accumulators flushed to FP64 after every slab.  The
   // diagonal tiles p = q are left to k_vdiag (FP64): they hold the large same-sign sums w v Phi_mu^2
