@@ -208,6 +208,27 @@ def bench_learned(args, torch):
     p4 = synth.make_problem(4)
     D4 = torch.from_numpy(p4.D).cuda()
     log("inputs: %s n_atoms=%d n_ao=%d n_points=%d" % (p4.name, p4.n_atoms, p4.n_ao, p4.n_points))
+    # the functional alone on this workload's (rho, sigma): analytic PBE (FP64) vs the network
+    plan = Plan.from_problem(p4, prec="fp32", xc="pbe")
+    r4, s4 = plan.eval_grid(D4)
+    plan.close()
+    torch.cuda.synchronize()
+    from paper_2605_10363_amd.plan import xc_eval
+    fn_ms = {}
+    for tag, fn in (("analytic", lambda: xc_eval("pbe", r4, s4, 1e-14)), ("mlp", lambda: net.forward(r4, s4))):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        fn_ms[tag] = e0.elapsed_time(e1) / 5
+    log("functional alone on %d points: analytic %.3f ms, network %.3f ms" % (r4.numel(), fn_ms["analytic"], fn_ms["mlp"]))
+    del r4, s4
+    torch.cuda.empty_cache()
     out_runs = {}
     for tag in ("analytic", "mlp"):
         plan = Plan.from_problem(p4, prec="fp32", xc="pbe")
@@ -236,7 +257,9 @@ def bench_learned(args, torch):
             "epochs": args.epochs,
             "train_s": round(train_s, 2), "final_loss": float(losses[-1]),
             "points_on_network": int(m["st"]["n_points_mlp"]), "fraction_on_network": m["st"]["n_points_mlp"] / p4.n_points,
-            "functional_ms": {"mlp": round(m["stage"]["xfunc"], 4), "analytic": round(a["stage"]["xfunc"], 4)},
+            "functional_kernel_ms": {"mlp": round(fn_ms["mlp"], 4), "analytic": round(fn_ms["analytic"], 4),
+                                     "what": "f, v_rho, v_sigma at every grid point of this workload, alone"},
+            "functional_and_z_stage_ms": {"mlp": round(m["stage"]["xfunc"], 4), "analytic": round(a["stage"]["xfunc"], 4)},
             "eval_ms": {"mlp": round(m["ms"], 4), "analytic": round(a["ms"], 4), "fp64_analytic": round(ms64, 4)},
             "E_xc": {"mlp": m["E"], "analytic": a["E"], "fp64_analytic": E64},
             "err_vs_analytic": {"E_xc": abs(m["E"] - a["E"]), "E_xc_rel": abs(m["E"] - a["E"]) / abs(a["E"]),
