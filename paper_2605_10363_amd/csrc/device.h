@@ -98,21 +98,30 @@ __device__ __forceinline__ void pw4(double d, double *p) {
   p[3] = p[2] * d;
 }
 
+// The basis tables are never written by a kernel: reading them through the constant address space lets
+// a wave-uniform access become a scalar load.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *ro(const T *p) {
+  return (const __attribute__((address_space(4))) T *)p;
+}
+
 // Calls emit(a, value, gx, gy, gz) for every AO a (local row 0..31) of tile p at (x, y, z).
 template <bool GRAD, class F>
 __device__ __forceinline__ void for_tile_aos(const BasisDev &B, int p, double x, double y, double z, F &&emit) {
-  const int s0 = B.tile_sh[2 * p], s1 = B.tile_sh[2 * p + 1];
+  const auto tile_sh = ro(B.tile_sh), sh_prim = ro(B.sh_prim), sh_l = ro(B.sh_l), sh_ao0 = ro(B.sh_ao0);
+  const auto sh_xyz = ro(B.sh_xyz), pexp = ro(B.pexp), pcoef = ro(B.pcoef);
+  const int s0 = tile_sh[2 * p], s1 = tile_sh[2 * p + 1];
   const int a_lo = p * kD, a_hi = a_lo + kD;
   for (int s = s0; s < s1; ++s) {
-    const double dx = x - B.sh_xyz[3 * s], dy = y - B.sh_xyz[3 * s + 1], dz = z - B.sh_xyz[3 * s + 2];
+    const double dx = x - sh_xyz[3 * s], dy = y - sh_xyz[3 * s + 1], dz = z - sh_xyz[3 * s + 2];
     const double r2 = dx * dx + dy * dy + dz * dz;
     double R = 0.0, R1 = 0.0;
-    for (int k = B.sh_prim[2 * s]; k < B.sh_prim[2 * s + 1]; ++k) {
-      const double e = B.pcoef[k] * exp(-B.pexp[k] * r2);
+    for (int k = sh_prim[2 * s]; k < sh_prim[2 * s + 1]; ++k) {
+      const double e = pcoef[k] * exp(-pexp[k] * r2);
       R += e;
-      if (GRAD) R1 -= 2.0 * B.pexp[k] * e;
+      if (GRAD) R1 -= 2.0 * pexp[k] * e;
     }
-    const int l = B.sh_l[s], ao0 = B.sh_ao0[s];
+    const int l = sh_l[s], ao0 = sh_ao0[s];
     const int cb = (l == 0) ? 0 : (l == 1 ? 1 : 4), nc = (l + 1) * (l + 2) / 2;
     double px[4], py[4], pz[4];
     pw4(dx, px);

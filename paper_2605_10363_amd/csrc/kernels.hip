@@ -164,6 +164,33 @@ __device__ __forceinline__ void lds_store_unit(T *dst, const uint4 &u) {
   for (int m = 0; m < Units<T>::E; ++m) dst[m] = src[m];
 }
 
+// Global -> LDS copies that bypass registers (global_load_lds_dwordx4): lane l of the wave writes its
+// 16 bytes at lds_wave + 16 l (measured on gfx950); lds_wave must be the same for the whole wave (it
+// goes to M0).  The copies count in vmcnt like vector loads, in issue order; the GEMM loops wait for
+// them with an explicit s_waitcnt and then meet at a bare s_barrier (a fence would wait for every copy
+// in flight).  Issued from inline assembly: the compiler would otherwise wait for all copies in flight
+// before every LDS read it cannot prove disjoint from them.  Its own vmcnt waits stay correct (copies
+// issued after one of its loads only make such a wait longer).
+typedef __attribute__((address_space(3))) void lds_void;
+__device__ __forceinline__ void dma16(const void *src, void *lds_wave) {
+  const uint32_t lds = __builtin_amdgcn_readfirstlane(
+      static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_void *)lds_wave)));
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
+               : "memory", "m0");
+}
+// s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+template <int N>
+__device__ __forceinline__ void wait_vm_lds() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
+}
+// s_barrier that the compiler may not move memory accesses across
+__device__ __forceinline__ void wg_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Persistent schedule: workgroup b serves queue b & 7 (its XCD) first, then the others in turn; a
 // queue's positions lo .. hi - 1 of `order` are handed out by an atomic counter.  Every workgroup
 // leaves once all 8 counters have passed their ends, so the grid always drains.
@@ -237,16 +264,19 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   typedef Mma<T> M;
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
-  constexpr int STAGES = (sizeof(T) == 4) ? 2 : 1;   // LDS stages of the K loop
+  constexpr bool F32 = sizeof(T) == 4;
+  // FP32: a ring of kRing LDS slots of one K step each (4 D tiles + one Phi tile, 32 KB).  FP64: one
+  // padded stage filled through registers.
+  constexpr int kRing = 4, kSlotF = 4 * kD * kD + kD * kG;
   constexpr int LDA_S = lda_s<T>(), LDB_S = ldb_s<T>();
   constexpr int kA = 128 * LDA_S, kB = 32 * LDB_S;
-  constexpr int kStageBytes = STAGES * (kA + kB) * int(sizeof(T));
-  static_assert(kStageBytes >= 2 * kD * kG * 8, "two FP64 X tiles must fit the staging area");
+  constexpr int kXsBytes = 4 * kD * kG * 8;   // the epilogue's X (FP64, 4 tiles) overlays the staging area
+  constexpr int kStageBytes = std::max(F32 ? kRing * kSlotF * 4 : (kA + kB) * int(sizeof(T)), kXsBytes);
   __shared__ __align__(16) unsigned char s_raw[kStageBytes];
   __shared__ int s_p[kMaxNp];
   __shared__ int s_list[kMaxNp];
   __shared__ int s_w[8];
-  __shared__ double s_acc[2][4][kG];
+  __shared__ double s_acc[4][4][kG];
   run_items(A.q, A.item0, A.n_items, [&](int64_t il) {
   const int64_t it = A.item0 + il;
   const int64_t r = A.xit_r[it];
@@ -260,12 +290,11 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   const T *phi = static_cast<const T *>(A.phi) - size_t(A.ret0) * (kD * kG);   // indexed by retained tile
   // (p, q) tile pair of the molecule -> its position in Dt / amax
   auto dtile = [&](int p, int q) { return size_t(mo.dt0) + size_t(p - mo.tile0) * mo.nt + (q - mo.tile0); };
-  T *sA = reinterpret_cast<T *>(s_raw);                 // [STAGES][kA]
-  T *sB = sA + STAGES * kA;                              // [STAGES][kB]
-  double *Xs = reinterpret_cast<double *>(s_raw);        // [2][32][kG] in the epilogue
+  T *sA = reinterpret_cast<T *>(s_raw);                 // FP64: [kA] D tiles, then [kB] Phi
+  T *sB = sA + kA;
+  double *Xs = reinterpret_cast<double *>(s_raw);        // [4][32][kG] in the epilogue
 
   for (int t = tid; t < np; t += NTX) s_p[t] = A.st.ret_p[k0 + t];
-  for (int e = tid; e < 8 * kG; e += NTX) (&s_acc[0][0][0])[e] = 0.0;
   __syncthreads();
 
   // ---- executable pairs of this chunk (eq. block_pair_filter), compacted by an exclusive prefix
@@ -316,112 +345,179 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
       for (int v = 0; v < 4; ++v) dacc[ti][tj][v] = 0.0;
     }
   const bool has_u = 4 * c + u < np;
-  constexpr int UA = (kD * kD) / E;   // 16-byte units per D tile
-  constexpr int UB = (kD * kG) / E;   // units per Phi tile
-  constexpr int NA = 4 * UA / NTX, NB = UB / NTX;
-  uint4 ra[NA], rb[NB];
-  auto fetch = [&](int e) {
-    const int t = s_list[e] & 0xffff;
-    const int q = s_p[t];
+  if constexpr (F32) {
+    // ---- FP32 operands.  Slot e % kRing holds step e: the 4 D tiles (p_u, q) as [row i][k] with the
+    // 16-byte units of row i XOR-swizzled (unit c at c ^ (i & 7)), then Phi_q as [k][point].  The copies
+    // go global -> LDS directly, kRing - 1 steps ahead; one barrier per step.  Index maps of the MFMA steps:
+    // step kk of a wave takes k = 8 (l / 16) + kk, so a lane reads the 8 values of its row of D with two
+    // 16-byte loads, and output column c of sub-tile tj is point 64 h + 4 c + tj, so a lane reads its 4
+    // values of a row of Phi_q with one 16-byte load.
+    float *ring = reinterpret_cast<float *>(s_raw);
+    const int ws = __builtin_amdgcn_readfirstlane(w), us = ws & 3;
+    const int m16 = l & 15, g = l >> 4;
+    const float *Df = reinterpret_cast<const float *>(Dt);
+    const float *Pf = reinterpret_cast<const float *>(phi);
+    auto issue = [&](int e) {
+      const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
+      float *dst = ring + (e & (kRing - 1)) * kSlotF + ws * 1024;   // this wave's 4 KB of the slot
+      if (ws < 4) {
+        // D tile (p, q) of chunk entry ws; an entry past the end of S_r loads entry np - 1 (valid
+        // memory, never multiplied: its wave has no executable pair)
+        const int q = __builtin_amdgcn_readfirstlane(s_p[t]);
+        const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + ws, np - 1)]);
+        const float *src = Df + dtile(pa, q) * (kD * kD);
 #pragma unroll
-    for (int m = 0; m < NA; ++m) {
-      const int un = tid + NTX * m, ww = un / UA, uu = un % UA;
-      ra[m] = make_uint4(0, 0, 0, 0);
-      if (4 * c + ww < np)
-        ra[m] = reinterpret_cast<const uint4 *>(Dt + dtile(s_p[4 * c + ww], q) * (kD * kD))[uu];
-    }
-    const uint4 *src = reinterpret_cast<const uint4 *>(phi + size_t(k0 + t) * (kD * kG));
-#pragma unroll
-    for (int m = 0; m < NB; ++m) rb[m] = src[tid + NTX * m];
-  };
-  auto stash = [&](int buf) {
-    T *a = sA + buf * kA;
-    T *b = sB + buf * kB;
-#pragma unroll
-    for (int m = 0; m < NA; ++m) {
-      const int un = tid + NTX * m, ww = un / UA, e0 = (un % UA) * E;
-      lds_store_unit<T>(&a[(32 * ww + e0 / kD) * LDA_S + e0 % kD], ra[m]);
-    }
-#pragma unroll
-    for (int m = 0; m < NB; ++m) {
-      const int e0 = (tid + NTX * m) * E;
-      lds_store_unit<T>(&b[(e0 / kG) * LDB_S + e0 % kG], rb[m]);
-    }
-  };
-  if (n_list > 0) {
-    fetch(0);
-    stash(0);
-  }
-  __syncthreads();
-  for (int e = 0; e < n_list; ++e) {
-    const int buf = (STAGES == 2) ? (e & 1) : 0;
-    const int mask = s_list[e] >> 16;
-    if (e + 1 < n_list) fetch(e + 1);
-    if ((mask >> u) & 1) {
-      const T *a = sA + buf * kA;
-      const T *b = sB + buf * kB;
-#pragma unroll 2
-      for (int kk = 0; kk < 8; ++kk) {
-        const int kc = 4 * kk + (l >> 4);
-        const T a0 = a[(32 * u + (l & 15)) * LDA_S + kc];
-        const T a1 = a[(32 * u + 16 + (l & 15)) * LDA_S + kc];
-#pragma unroll
-        for (int tj = 0; tj < 4; ++tj) {
-          const T bv = b[kc * LDB_S + 64 * h + 16 * tj + (l & 15)];
-          acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
-          acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
+        for (int m = 0; m < 4; ++m) {
+          const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          dma16(src + i * kD + 4 * cu, dst + 256 * m);
         }
-        if (sizeof(T) == 4 && kk % kXFlush == kXFlush - 1) {
+      } else {
+        const float *src = Pf + size_t(k0 + t) * (kD * kG) + 1024 * (ws - 4);
 #pragma unroll
-          for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-            for (int tj = 0; tj < 4; ++tj) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
-              acc[ti][tj] = acc_t{};
-            }
-        }
+        for (int m = 0; m < 4; ++m) dma16(src + 4 * (64 * m + l), dst + 256 * m);
       }
-    }
-    if (STAGES == 1) {
-      __syncthreads();
-      if (e + 1 < n_list) stash(0);
-    } else if (e + 1 < n_list) {
-      stash(buf ^ 1);
-    }
-    __syncthreads();
-  }
-
-  // ---- epilogue: rho_i += sum_mu Phi_mu,i X_mu,i and grad rho_i += 2 sum_mu grad Phi_mu,i X_mu,i over
-  // the AOs of the chunk's tiles.  X (FP64) goes through LDS two tiles at a time; then one thread per
-  // (tile, point) evaluates the tile's shells once.
-  const int slot_h = (tid >> 7) & 1, j = tid & (kG - 1);
-  const bool worker = tid < 2 * kG;
-  double px = 0, py = 0, pz = 0;
-  if (GGA && worker) {
-    const int64_t ip = r * kG + j;
-    px = A.g.x[ip];
-    py = A.g.y[ip];
-    pz = A.g.z[ip];
-  }
-  for (int round = 0; round < 2; ++round) {
-    if ((u >> 1) == round && has_u) {
-      double *Xw = Xs + (u & 1) * (kD * kG);
+    };
+    struct Frag {
+      f4 a[2][2];   // rows 16 ti + l % 16 of tile u, k = 8 (l / 16) + 4 hh .. + 3
+      f4 b[8];      // row k = 8 (l / 16) + kk of Phi_q, points 64 h + 4 (l % 16) .. + 3
+    };
+    auto frag = [&](int e, Frag &F) {
+      const float *sl = ring + (e & (kRing - 1)) * kSlotF;
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 4; ++tj)
+        for (int hh = 0; hh < 2; ++hh)
+          F.a[ti][hh] = *reinterpret_cast<const f4 *>(sl + us * (kD * kD) + (16 * ti + m16) * kD +
+                                                      4 * ((2 * g + hh) ^ (m16 & 7)));
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            Xw[(16 * ti + M::row(v, l)) * kG + 64 * h + 16 * tj + (l & 15)] = dacc[ti][tj][v] + double(acc[ti][tj][v]);
+      for (int kk = 0; kk < 8; ++kk)
+        F.b[kk] = *reinterpret_cast<const f4 *>(sl + 4 * kD * kD + (8 * g + kk) * kG + 64 * h + 4 * m16);
+    };
+    for (int j = 0; j < kRing - 1 && j < n_list; ++j) issue(j);
+    // step e: wait until this wave's copies of step e have landed (later steps may stay in flight) and
+    // its reads of step e - 1 are done; after the barrier the slot of step e - 1 is free for step
+    // e + kRing - 1
+    for (int e = 0; e < n_list; ++e) {
+      const int ahead = min(n_list, e + kRing - 1) - (e + 1);
+      if (ahead >= 2) wait_vm_lds<8>(); else if (ahead == 1) wait_vm_lds<4>(); else wait_vm_lds<0>();
+      wg_barrier();
+      if (e + kRing - 1 < n_list) issue(e + kRing - 1);
+      const int mask = __builtin_amdgcn_readfirstlane(s_list[e] >> 16);
+      if ((mask >> us) & 1) {
+        Frag F;
+        frag(e, F);
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const float a0 = F.a[0][kk >> 2][kk & 3], a1 = F.a[1][kk >> 2][kk & 3];
+#pragma unroll
+          for (int tj = 0; tj < 4; ++tj) {
+            acc[0][tj] = M::mma(a0, F.b[kk][tj], acc[0][tj]);
+            acc[1][tj] = M::mma(a1, F.b[kk][tj], acc[1][tj]);
+          }
+          if (kk % kXFlush == kXFlush - 1) {
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+              for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
+                acc[ti][tj] = acc_t{};
+              }
+          }
+        }
+      }
     }
     __syncthreads();
-    const int slot = 4 * c + 2 * round + slot_h;
-    if (worker && slot < np) {
-      const double *Xw = Xs + slot_h * (kD * kG);
-      double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  } else {
+    constexpr int UA = (kD * kD) / E;   // 16-byte units per D tile
+    constexpr int UB = (kD * kG) / E;   // units per Phi tile
+    constexpr int NA = 4 * UA / NTX, NB = UB / NTX;
+    uint4 ra[NA], rb[NB];
+    auto fetch = [&](int e) {
+      const int t = s_list[e] & 0xffff;
+      const int q = s_p[t];
+#pragma unroll
+      for (int m = 0; m < NA; ++m) {
+        const int un = tid + NTX * m, ww = un / UA, uu = un % UA;
+        ra[m] = make_uint4(0, 0, 0, 0);
+        if (4 * c + ww < np)
+          ra[m] = reinterpret_cast<const uint4 *>(Dt + dtile(s_p[4 * c + ww], q) * (kD * kD))[uu];
+      }
+      const uint4 *src = reinterpret_cast<const uint4 *>(phi + size_t(k0 + t) * (kD * kG));
+#pragma unroll
+      for (int m = 0; m < NB; ++m) rb[m] = src[tid + NTX * m];
+    };
+    auto stash = [&]() {
+      T *a = sA;
+      T *b = sB;
+#pragma unroll
+      for (int m = 0; m < NA; ++m) {
+        const int un = tid + NTX * m, ww = un / UA, e0 = (un % UA) * E;
+        lds_store_unit<T>(&a[(32 * ww + e0 / kD) * LDA_S + e0 % kD], ra[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < NB; ++m) {
+        const int e0 = (tid + NTX * m) * E;
+        lds_store_unit<T>(&b[(e0 / kG) * LDB_S + e0 % kG], rb[m]);
+      }
+    };
+    if (n_list > 0) {
+      fetch(0);
+      stash();
+    }
+    __syncthreads();
+    for (int e = 0; e < n_list; ++e) {
+      const int mask = s_list[e] >> 16;
+      if (e + 1 < n_list) fetch(e + 1);
+      if ((mask >> u) & 1) {
+        const T *a = sA;
+        const T *b = sB;
+#pragma unroll 2
+        for (int kk = 0; kk < 8; ++kk) {
+          const int kc = 4 * kk + (l >> 4);
+          const T a0 = a[(32 * u + (l & 15)) * LDA_S + kc];
+          const T a1 = a[(32 * u + 16 + (l & 15)) * LDA_S + kc];
+#pragma unroll
+          for (int tj = 0; tj < 4; ++tj) {
+            const T bv = b[kc * LDB_S + 64 * h + 16 * tj + (l & 15)];
+            acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
+            acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
+          }
+        }
+      }
+      __syncthreads();
+      if (e + 1 < n_list) stash();
+      __syncthreads();
+    }
+  }
+
+  // ---- epilogue: rho_i += sum_mu Phi_mu,i X_mu,i and grad rho_i += 2 sum_mu grad Phi_mu,i X_mu,i over
+  // the AOs of the chunk's tiles.  X (FP64) of the 4 tiles goes through LDS; then one thread per (tile,
+  // point) evaluates the tile's shells once, in FP64 (a wave shares one tile, so the shell data are
+  // scalar loads), and the 4 tiles are summed in a fixed order.
+  const int slot_w = tid >> 7, j = tid & (kG - 1);
+  if (has_u) {
+    double *Xw = Xs + u * (kD * kG);
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          Xw[(16 * ti + M::row(v, l)) * kG + 64 * h + (F32 ? 4 * (l & 15) + tj : 16 * tj + (l & 15))] =
+              dacc[ti][tj][v] + double(acc[ti][tj][v]);
+  }
+  __syncthreads();
+  {
+    const int slot = 4 * c + slot_w;
+    double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    if (slot < np) {
+      const double *Xw = Xs + slot_w * (kD * kG);
       if (GGA) {
-        for_tile_aos<true>(A.B, s_p[slot], px, py, pz, [&](int a, double v, double gx, double gy, double gz) {
+        const int64_t ip = r * kG + j;
+        const int pt = __builtin_amdgcn_readfirstlane(s_p[slot]);
+        for_tile_aos<true>(A.B, pt, A.g.x[ip], A.g.y[ip], A.g.z[ip], [&](int a, double v, double gx, double gy,
+                                                                          double gz) {
           const double X = Xw[a * kG + j];
           s0 += v * X;
           sx += gx * X;
@@ -437,17 +533,18 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
           for (int a = 0; a < kD; ++a) s0 += double(ph[a * kG]) * Xw[a * kG + j];
         }
       }
-      s_acc[slot_h][0][j] += s0;
-      s_acc[slot_h][1][j] += 2.0 * sx;
-      s_acc[slot_h][2][j] += 2.0 * sy;
-      s_acc[slot_h][3][j] += 2.0 * sz;
     }
-    __syncthreads();
+    s_acc[slot_w][0][j] = s0;
+    s_acc[slot_w][1][j] = 2.0 * sx;
+    s_acc[slot_w][2][j] = 2.0 * sy;
+    s_acc[slot_w][3][j] = 2.0 * sz;
   }
+  __syncthreads();
   if (tid < kG) {
     double *out = A.part + size_t(il) * (4 * kG);
 #pragma unroll
-    for (int cp = 0; cp < (GGA ? 4 : 1); ++cp) out[cp * kG + tid] = s_acc[0][cp][tid] + s_acc[1][cp][tid];
+    for (int cp = 0; cp < (GGA ? 4 : 1); ++cp)
+      out[cp * kG + tid] = (s_acc[0][cp][tid] + s_acc[2][cp][tid]) + (s_acc[1][cp][tid] + s_acc[3][cp][tid]);
   }
   double pd = wave_sum(double(pairs));
   if (l == 0 && pd > 0) atomicAdd(&A.counters[0], (unsigned long long)(pd + 0.5));
