@@ -247,12 +247,8 @@ constexpr int NTX = 512;   // threads per X workgroup: 8 waves, each 32 rows x 6
 #ifndef KLDI_XFLUSH
 #define KLDI_XFLUSH 8
 #endif
-#ifndef KLDI_VFLUSH
-#define KLDI_VFLUSH 8
-#endif
 constexpr int kXFlush = KLDI_XFLUSH;
-constexpr int kVFlush = KLDI_VFLUSH;
-static_assert(8 % kXFlush == 0 && 8 % kVFlush == 0, "flush intervals must divide the 8 steps of a slab");
+static_assert(8 % kXFlush == 0, "the flush interval must divide the 8 MFMA steps of a K tile");
 
 // One workgroup per (grid block r, chunk c of 4 retained output tiles): X_pr = sum_q D_pq Phi_qr for
 // the 4 tiles p = S_r[4c .. 4c+3], then the chunk's contribution to rho and grad rho.  Wave w owns
@@ -717,13 +713,18 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   constexpr int E = Units<T>::E;
   constexpr int LDA_S = lda_s<T>();
   constexpr int kS = 128 * LDA_S;  // one A or B stage (4 tiles x 32 rows x 32 points)
-  // FP32 operands: M = Phi Z^T on FP32 MFMA, accumulators flushed to FP64 after every slab.  The
-  // diagonal tiles p = q are left to k_vdiag (FP64): they hold the large same-sign sums w v Phi_mu^2
+  // FP32 operands: M = Phi Z^T on FP32 MFMA, accumulators flushed to FP64 after every 32-point
+  // sub-step.  The diagonal tiles p = q are left to k_vdiag (FP64): they hold the large same-sign sums w v Phi_mu^2
   // whose FP32 rounding, correlated over the points of one radial shell where Phi takes one value,
   // would dominate the error of the mixed path.
-  constexpr bool SPLIT = sizeof(T) == 4;
-  __shared__ __align__(16) T sA[2 * kS];
-  __shared__ __align__(16) T sB[2 * kS];
+  constexpr bool F32 = sizeof(T) == 4;
+  // FP32: a ring of kRing LDS slots, one 32-point sub-step each (4 Phi slabs + 4 Z slabs of 32 x 32,
+  // 32 KB).  FP64: two padded stages filled through registers.
+  constexpr int kRing = 4, kSlab = kD * kD, kSlotF = 8 * kSlab;
+  constexpr int kStageBytes = F32 ? kRing * kSlotF * 4 : 4 * kS * int(sizeof(T));
+  __shared__ __align__(16) unsigned char s_raw[kStageBytes];
+  T *sA = reinterpret_cast<T *>(s_raw);    // FP64: [2][kS]
+  T *sB = sA + 2 * kS;                     // FP64: [2][kS]
   __shared__ int s_m[NTV];
   __shared__ int s_ip[NTV], s_iq[NTV];
   __shared__ long long s_bo[NTV];
@@ -748,8 +749,13 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
     }
   unsigned long long pairs = 0;
   int any = 0;
-  // column tile (0 or 1 of this wave's two) that is the diagonal tile p = q, or -1
-  const int dcol = (SPLIT && it.pc == it.qc && (u >> 1) == h) ? (u & 1) : -1;
+  // FP32: wave w owns the tile pairs (a, b) = (2 (w >> 2) + P, (w - a) & 3), P = 0, 1: the two waves
+  // of a SIMD (w, w + 4) take the 4 pairs with a + b = w (mod 4), one of every row and column of the
+  // 4 x 4 chunk pair, so a tile missing from a grid block costs every SIMD alike
+  const int ws = __builtin_amdgcn_readfirstlane(w);
+  const int pa0 = 2 * (ws >> 2), pb0 = (ws - pa0) & 3, pb1 = (ws - pa0 - 1) & 3;
+  // FP32: the diagonal pairs (a, a) of a diagonal chunk pair are k_vdiag's (FP64)
+  const int wdiag = (F32 && it.pc == it.qc) ? (((pa0 == pb0) ? 1 : 0) | ((pa0 + 1 == pb1) ? 2 : 0)) : 0;
 
   for (int base = it.r0; base < it.r1; base += NTV) {
     const int r = base + tid;
@@ -776,87 +782,147 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
     __syncthreads();
     any |= tot;
 
-    // stages s = 4 e + sub: entry e of the compacted list, points 32 sub .. 32 sub + 31
-    constexpr int UR = kD / E;          // units per 32-element row slice
-    constexpr int UT = kD * UR;         // units per 32 x 32 slab
-    constexpr int NU = 8 * UT / NTV;    // units per thread (4 A slabs + 4 B slabs)
-    uint4 rv[NU];
-    int rmask = 0;
-    auto fetch = [&](int st) {
-      const int e = st >> 2, sub = st & 3;
-      const int m = s_m[e], ip = s_ip[e], iq = s_iq[e];
-      const int64_t bo = s_bo[e];
-      rmask = 0;
+    if constexpr (F32) {
+      // sub-step st = 4 e + sub: entry e of the compacted list, points 32 sub .. 32 sub + 31.  Slot st %
+      // kRing: slab a < 4 is Phi_(4pc+a) and slab 4 + b is Z_(4qc+b), each [row i][point] with the
+      // 16-byte units of row i XOR-swizzled (unit c at c ^ (i & 7)); wave w copies slab w, global ->
+      // LDS directly, kRing - 1 sub-steps ahead, and only where the slab's tile has an executable pair.
+      // MFMA step kk takes point 8 (l / 16) + kk of the sub-step, so a lane reads the 8 values of its
+      // row of a slab with two 16-byte loads.
+      float *ring = reinterpret_cast<float *>(s_raw);
+      const float *Pf = reinterpret_cast<const float *>(phi);
+      const float *Zf = reinterpret_cast<const float *>(zws);
+      const int m16 = l & 15, g = l >> 4;
+      const int nst = 4 * tot;
+      auto issue = [&](int st) -> int {
+        const int e = st >> 2, sub = st & 3;
+        const int m = __builtin_amdgcn_readfirstlane(s_m[e]);
+        const int slab = ws & 3;
+        const bool need = ws < 4 ? ((m >> (4 * slab)) & 15) != 0 : ((m >> slab) & 0x1111) != 0;
+        if (!need) return 0;
+        const int info = __builtin_amdgcn_readfirstlane(ws < 4 ? s_ip[e] : s_iq[e]);
+        const long long bo = s_bo[e];
+        const float *src = (ws < 4 ? Pf : Zf) + size_t(bo + tile_pos(info, slab)) * (kD * kG) + 32 * sub;
+        float *dst = ring + (st & (kRing - 1)) * kSlotF + ws * kSlab;
 #pragma unroll
-      for (int k = 0; k < NU; ++k) {
-        const int un = tid + NTV * k, which = un / UT, uu = un % UT;
-        const int i = uu / UR, j0 = (uu % UR) * E;
-        const int slot = which & 3;
-        // a row tile is needed if any of its pairs runs, a column tile likewise
-        const bool need = (which < 4) ? ((m >> (4 * slot)) & 15) != 0 : ((m >> slot) & 0x1111) != 0;
-        if (need) {
-          const int pos = tile_pos(which < 4 ? ip : iq, slot);
-          const T *src = ((which < 4) ? phi : zws) + size_t(bo + pos) * (kD * kG) + i * kG + 32 * sub + j0;
-          rv[k] = *reinterpret_cast<const uint4 *>(src);
-          rmask |= 1 << k;
+        for (int k = 0; k < 4; ++k) {
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          dma16(src + i * kG + 4 * cu, dst + 256 * k);
         }
-      }
-    };
-    auto stash = [&](int buf) {
+        return 1;
+      };
+      // bit k of hist: this wave copied sub-step st + k
+      int hist = 0;
+      for (int j = 0; j < kRing - 1; ++j)
+        if (j < nst) hist |= issue(j) << j;
+      for (int st = 0; st < nst; ++st) {
+        // this wave's copies of sub-step st have landed (those of st + 1, st + 2 may stay in flight) and
+        // its reads of st - 1 are done; after the barrier the slot of st - 1 takes sub-step st + 3
+        const int ahead = ((hist >> 1) & 1) + ((hist >> 2) & 1);
+        if (ahead == 2) wait_vm_lds<8>(); else if (ahead == 1) wait_vm_lds<4>(); else wait_vm_lds<0>();
+        wg_barrier();
+        const int nb = (st + kRing - 1 < nst) ? issue(st + kRing - 1) : 0;
+        hist = (hist >> 1) | (nb << (kRing - 2));
+        const int m = __builtin_amdgcn_readfirstlane(s_m[st >> 2]);
+        const float *sl = ring + (st & (kRing - 1)) * kSlotF;
 #pragma unroll
-      for (int k = 0; k < NU; ++k) {
-        if (!((rmask >> k) & 1)) continue;
-        const int un = tid + NTV * k, which = un / UT, uu = un % UT;
-        const int i = uu / UR, j0 = (uu % UR) * E;
-        T *dst = (which < 4) ? &sA[buf * kS + (32 * which + i) * LDA_S + j0]
-                             : &sB[buf * kS + (32 * (which - 4) + i) * LDA_S + j0];
-        lds_store_unit<T>(dst, rv[k]);
-      }
-    };
-    const int nst = 4 * tot;
-    if (nst > 0) {
-      fetch(0);
-      stash(0);
-    }
-    __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-      const int buf = st & 1;
-      const int wm = (s_m[st >> 2] >> (4 * u + 2 * h)) & 3;   // this wave's two column tiles
-      if (st + 1 < nst) fetch(st + 1);
-      if (wm) {
-        const T *a = sA + buf * kS;
-        const T *b = sB + buf * kS;
-        // FP32 tiles (all but the diagonal one)
-        const int wf = (SPLIT && dcol >= 0) ? (wm & ~(1 << dcol)) : wm;
-#pragma unroll 2
-        for (int kk = 0; kk < 8; ++kk) {
-          const int kc = 4 * kk + (l >> 4);
-          const T a0 = a[(32 * u + (l & 15)) * LDA_S + kc];
-          const T a1 = a[(32 * u + 16 + (l & 15)) * LDA_S + kc];
+        for (int P = 0; P < 2; ++P) {
+          const int a = pa0 + P, b = P ? pb1 : pb0;
+          if (!((m >> (4 * a + b)) & 1) || ((wdiag >> P) & 1)) continue;
+          f4 fa[2][2], fb[2][2];
 #pragma unroll
-          for (int tj = 0; tj < 4; ++tj) {
-            if ((wf >> (tj >> 1)) & 1) {
-              const T bv = b[(64 * h + 16 * tj + (l & 15)) * LDA_S + kc];
-              acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
-              acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+              const int off = (16 * t + m16) * kD + 4 * ((2 * g + hh) ^ (m16 & 7));
+              fa[t][hh] = *reinterpret_cast<const f4 *>(sl + a * kSlab + off);
+              fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + off);
             }
-          }
-          if (sizeof(T) == 4 && kk % kVFlush == kVFlush - 1) {
-            // FP32 accumulation spans 4 kVFlush points; the running sum over those spans, the
-            // slabs and the grid blocks is FP64
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
             for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-              for (int tj = 0; tj < 4; ++tj) {
+              for (int tj = 0; tj < 2; ++tj)
+                acc[P][2 * ti + tj] = M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3], acc[P][2 * ti + tj]);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
-                acc[ti][tj] = acc_t{};
-              }
+          for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dacc[P][q][v] += double(acc[P][q][v]);
+            acc[P][q] = acc_t{};
           }
         }
       }
-      if (st + 1 < nst) stash(buf ^ 1);
       __syncthreads();
+    } else {
+      // stages s = 4 e + sub: entry e of the compacted list, points 32 sub .. 32 sub + 31
+      constexpr int UR = kD / E;          // units per 32-element row slice
+      constexpr int UT = kD * UR;         // units per 32 x 32 slab
+      constexpr int NU = 8 * UT / NTV;    // units per thread (4 A slabs + 4 B slabs)
+      uint4 rv[NU];
+      int rmask = 0;
+      auto fetch = [&](int st) {
+        const int e = st >> 2, sub = st & 3;
+        const int m = s_m[e], ip = s_ip[e], iq = s_iq[e];
+        const int64_t bo = s_bo[e];
+        rmask = 0;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+          const int un = tid + NTV * k, which = un / UT, uu = un % UT;
+          const int i = uu / UR, j0 = (uu % UR) * E;
+          const int slot = which & 3;
+          // a row tile is needed if any of its pairs runs, a column tile likewise
+          const bool need = (which < 4) ? ((m >> (4 * slot)) & 15) != 0 : ((m >> slot) & 0x1111) != 0;
+          if (need) {
+            const int pos = tile_pos(which < 4 ? ip : iq, slot);
+            const T *src = ((which < 4) ? phi : zws) + size_t(bo + pos) * (kD * kG) + i * kG + 32 * sub + j0;
+            rv[k] = *reinterpret_cast<const uint4 *>(src);
+            rmask |= 1 << k;
+          }
+        }
+      };
+      auto stash = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+          if (!((rmask >> k) & 1)) continue;
+          const int un = tid + NTV * k, which = un / UT, uu = un % UT;
+          const int i = uu / UR, j0 = (uu % UR) * E;
+          T *dst = (which < 4) ? &sA[buf * kS + (32 * which + i) * LDA_S + j0]
+                                 : &sB[buf * kS + (32 * (which - 4) + i) * LDA_S + j0];
+          lds_store_unit<T>(dst, rv[k]);
+        }
+      };
+      const int nst = 4 * tot;
+      if (nst > 0) {
+        fetch(0);
+        stash(0);
+      }
+      __syncthreads();
+      for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        const int wm = (s_m[st >> 2] >> (4 * u + 2 * h)) & 3;   // this wave's two column tiles
+        if (st + 1 < nst) fetch(st + 1);
+        if (wm) {
+          const T *a = sA + buf * kS;
+          const T *b = sB + buf * kS;
+#pragma unroll 2
+          for (int kk = 0; kk < 8; ++kk) {
+            const int kc = 4 * kk + (l >> 4);
+            const T a0 = a[(32 * u + (l & 15)) * LDA_S + kc];
+            const T a1 = a[(32 * u + 16 + (l & 15)) * LDA_S + kc];
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj) {
+              if ((wm >> (tj >> 1)) & 1) {
+                const T bv = b[(64 * h + 16 * tj + (l & 15)) * LDA_S + kc];
+                acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
+                acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
+              }
+            }
+          }
+        }
+        if (st + 1 < nst) stash(buf ^ 1);
+        __syncthreads();
+      }
     }
   }
   if (!any) {
@@ -866,17 +932,31 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   // every thread has read the entry metadata of the last compaction round (the K loop ends with a
   // barrier), so the next item of a persistent workgroup may overwrite it
   double *out = A.vpart + size_t(item) * (128 * 128);
+  if constexpr (F32) {
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+    for (int P = 0; P < 2; ++P) {
+      if ((wdiag >> P) & 1) continue;         // written by k_vdiag
+      const int a = pa0 + P, b = P ? pb1 : pb0;
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) {
-      if ((tj >> 1) == dcol) continue;        // written by k_vdiag
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 32 * u + 16 * ti + M::row(v, l), col = 64 * h + 16 * tj + (l & 15);
-        out[row * 128 + col] = dacc[ti][tj][v] + double(acc[ti][tj][v]);
-      }
+        for (int v = 0; v < 4; ++v) {
+          const int row = 32 * a + 16 * (q >> 1) + M::row(v, l), col = 32 * b + 16 * (q & 1) + (l & 15);
+          out[row * 128 + col] = dacc[P][q][v] + double(acc[P][q][v]);
+        }
     }
+  } else {
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 32 * u + 16 * ti + M::row(v, l), col = 64 * h + 16 * tj + (l & 15);
+          out[row * 128 + col] = dacc[ti][tj][v] + double(acc[ti][tj][v]);
+        }
+      }
+  }
   if (tid == 0) A.vflag[item] = 1;
   double pd = wave_sum(double(pairs));
   if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
