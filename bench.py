@@ -285,6 +285,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--v-segment", type=int, default=0, help="grid blocks per Vxc segment (0 = plan's choice)")
+    ap.add_argument("--schedule", default="grid", choices=["grid", "queue", "auto"],
+                    help="work-item schedule of the GEMM kernels (auto: the plan's autotuner picks it and the "
+                         "Vxc segment length, outside the timed region)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM-counter calibration for profiling)")
     args = ap.parse_args()
@@ -317,8 +320,12 @@ def main():
     res = {}
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
         t0 = time.time()
-        plan = Plan.from_problem(p, prec=prec, v_segment=args.v_segment)
+        plan = Plan.from_problem(p, prec=prec, v_segment=args.v_segment,
+                                 schedule="grid" if args.schedule == "auto" else args.schedule)
+        tune = plan.autotune(D, reps=2) if args.schedule == "auto" else None
         info = plan.info()
+        if tune is not None:
+            log("%s autotune: %s" % (prec, tune))
         log("%s plan: %.0f ms, retained fraction %.4f, n_ret %d, max tiles/block %d, %d V items, %.1f GB" % (
             prec, info["plan_ms"], info["retained_fraction"], info["n_retained_tiles"], info["max_tiles_per_block"],
             info["n_v_items"], info["workspace_bytes"] / 1e9))

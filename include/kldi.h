@@ -98,9 +98,8 @@ typedef struct {
 /* How the block-GEMM stages distribute their work items (tasks of Sec. III-D) over the GPU. */
 typedef enum {
   KLDI_SCHED_GRID = 0,      /* one workgroup per work item; the hardware dispatcher balances      */
-  KLDI_SCHED_QUEUE = 1      /* persistent workgroups pull items from 8 per-XCD queues (items of a
-                               queue share L2; each queue ordered by decreasing estimated cost) and
-                               take from the other queues when theirs is empty                     */
+  KLDI_SCHED_QUEUE = 1      /* 8 per-XCD queues of about equal estimated cost (items of a queue
+                               share L2), each ordered by decreasing cost; one workgroup per item */
 } kldi_schedule;
 
 typedef struct {

@@ -1,6 +1,6 @@
 // Host side of libkldi: the C ABI, argument validation, the per-geometry plan (reordering, tiling,
 // shell radii, screening, retained-block lists) for one molecule or a batch of molecules, the work
-// schedule (work lists, persistent-kernel queues, workspaces), graph capture and the autotuner.
+// schedule (work lists, per-XCD queue orders, workspaces), graph capture and the autotuner.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -370,8 +370,8 @@ void append(std::vector<T> &dst, const std::vector<T> &src, F &&map) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// Work schedule: X and Vxc work lists for a Vxc segment length, grid chunks, queue orders of the
-// persistent kernels, and the workspaces sized by them.  Rebuilt by the autotuner.
+// Work schedule: X and Vxc work lists for a Vxc segment length, grid chunks, the per-XCD queue
+// orders, and the workspaces sized by them.  Rebuilt by the autotuner.
 // ------------------------------------------------------------------------------------------------
 void visit_v_items(const Plan &P, const std::vector<std::vector<int>> &blk_chunks, int seg,
                    const std::function<void(int m, int lpair, int r0, int r1)> &emit) {
@@ -571,7 +571,7 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
     max_vm = std::max(max_vm, P.vmoff_h[C.blk1] - P.vmoff_h[C.blk0]);
   }
 
-  // queues of the persistent schedule, per grid chunk
+  // per-XCD queue orders, per grid chunk
   const size_t nch = P.chunks_h.size();
   {
     // Vxc items of diagonal chunk pairs, per grid chunk (their diagonal tiles run in FP64)
@@ -614,6 +614,13 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
       }
       make_queues(C.vit0, C.vit1, vs, vc, vorder, &vqoff[9 * ci]);
     }
+    P.xq.maxlen_h.assign(nch, 0);
+    P.vq.maxlen_h.assign(nch, 0);
+    for (size_t ci = 0; ci < nch; ++ci)
+      for (int x = 0; x < 8; ++x) {
+        P.xq.maxlen_h[ci] = std::max(P.xq.maxlen_h[ci], xqoff[9 * ci + x + 1] - xqoff[9 * ci + x]);
+        P.vq.maxlen_h[ci] = std::max(P.vq.maxlen_h[ci], vqoff[9 * ci + x + 1] - vqoff[9 * ci + x]);
+      }
     P.xq.order = dev_upload(P, xorder, true);
     P.xq.qoff = dev_upload(P, xqoff, true);
     P.vq.order = dev_upload(P, vorder, true);
@@ -634,7 +641,6 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
   E.vpart = dev_alloc<double>(P, P.items_h.size() * 16384, true);
   E.vflag = dev_alloc<int>(P, P.items_h.size(), true);
   E.vmask = dev_alloc<unsigned short>(P, size_t(max_vm), true);
-  E.qcnt = dev_alloc<int>(P, 16 * nch, true);
 }
 
 // ------------------------------------------------------------------------------------------------

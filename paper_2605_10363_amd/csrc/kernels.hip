@@ -20,8 +20,8 @@
 //   k_vreduce  FP64 sum of the segment partials in fixed order
 //   k_vsym     Vxc = M + M^T (GGA) or mirrored 2M (LDA), back to the caller's AO order
 //   k_esum     E_xc of each molecule as a fixed-order FP64 sum of its per-block partials
-// The two GEMM kernels run either one workgroup per work item or as persistent workgroups pulling items
-// from per-XCD queues (kldi_schedule).
+// The two GEMM kernels run one workgroup per work item, in item order or in per-XCD queue order
+// (kldi_schedule).
 #include <algorithm>
 
 #include <hip/hip_bf16.h>
@@ -69,11 +69,9 @@ __global__ __launch_bounds__(kG) void k_screen(BasisDev B, GridDev g, const int 
 // ------------------------------------------------------------------------------------------------
 // per-evaluation kernels
 // ------------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_begin(IoDev *cell, IoDev io, unsigned long long *counters, int *qcnt,
-                                             int nq) {
+__global__ __launch_bounds__(NT) void k_begin(IoDev *cell, IoDev io, unsigned long long *counters) {
   if (threadIdx.x == 0) *cell = io;
   if (threadIdx.x < 4) counters[threadIdx.x] = 0ull;
-  for (int i = threadIdx.x; i < nq; i += NT) qcnt[i] = 0;
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -191,13 +189,13 @@ __device__ __forceinline__ void wg_barrier() {
   asm volatile("" ::: "memory");
 }
 
-// Persistent schedule: workgroup b serves queue b & 7 (its XCD) first, then the others in turn; a
-// queue's positions lo .. hi - 1 of `order` are handed out by an atomic counter.  Every workgroup
-// leaves once all 8 counters have passed their ends, so the grid always drains.
+// Work-item schedules.  Grid: workgroup b runs item xcd_remap(b) (contiguous item ranges per XCD).
+// Queue: 8 per-XCD queues of about equal cost, each ordered by decreasing cost; workgroup b runs
+// position b / 8 of queue b % 8 (the dispatcher places workgroup b on XCD b % 8), or nothing past the
+// end of its queue.
 struct QArgs {
-  const int *order;        // item ids in queue order (NULL: one workgroup per item)
+  const int *order;        // item ids in queue order (NULL: grid schedule)
   const int64_t *qoff;     // [9] queue boundaries of this launch
-  int *qcnt;               // [8] counters of this launch
 };
 
 template <class F>
@@ -207,20 +205,9 @@ __device__ __forceinline__ void run_items(const QArgs &q, int64_t item0, int64_t
     if (il < n_items) run(il);
     return;
   }
-  __shared__ int s_next;
-  const int x0 = blockIdx.x & 7;
-  for (int k = 0; k < 8; ++k) {
-    const int qx = (x0 + k) & 7;
-    const int64_t lo = q.qoff[qx], hi = q.qoff[qx + 1];
-    for (;;) {
-      if (threadIdx.x == 0) s_next = atomicAdd(&q.qcnt[qx], 1);
-      __syncthreads();
-      const int64_t pos = lo + s_next;
-      __syncthreads();
-      if (pos >= hi) break;
-      run(int64_t(q.order[pos]) - item0);
-    }
-  }
+  const int qx = blockIdx.x & 7;
+  const int64_t pos = q.qoff[qx] + (blockIdx.x >> 3);
+  if (pos < q.qoff[qx + 1]) run(int64_t(q.order[pos]) - item0);
 }
 
 struct XArgs {
@@ -929,8 +916,6 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
     if (tid == 0) A.vflag[item] = 0;
     return;
   }
-  // every thread has read the entry metadata of the last compaction round (the K loop ends with a
-  // barrier), so the next item of a persistent workgroup may overwrite it
   double *out = A.vpart + size_t(item) * (128 * 128);
   if constexpr (F32) {
 #pragma unroll
@@ -1080,13 +1065,6 @@ __global__ __launch_bounds__(NT) void k_esum(const MolDev *mol, const double *__
   if (threadIdx.x == 0) io->exc[blockIdx.x] = s[0];
 }
 
-// Persistent grid of a GEMM launch: resident workgroups over the chip, at most one per item, a
-// multiple of 8 so every XCD queue has servers.
-int64_t persistent_grid(int occ, int n_cu, int64_t n_items) {
-  const int64_t full = int64_t(std::max(occ, 1)) * std::max(n_cu, 8);
-  return 8 * ((std::min(full, n_items) + 7) / 8);
-}
-
 template <class T>
 hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
   const EvalDev &E = P.ev;
@@ -1105,7 +1083,6 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
     mark(3);
     mark(4);
   }
-  const int occ_x = queue ? occupancy_x(P) : 0, occ_v = queue ? occupancy_v(P) : 0;
   for (size_t ci = 0; ci < P.chunks_h.size(); ++ci) {
     const GridChunk &C = P.chunks_h[ci];
     const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nxit = C.xit1 - C.xit0, nvit = C.vit1 - C.vit0;
@@ -1128,11 +1105,11 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
     xa.counters = E.counters;
     xa.t_b = P.opts.t_b;
     xa.t_d = P.opts.t_d;
-    xa.q = QArgs{nullptr, nullptr, nullptr};
+    xa.q = QArgs{nullptr, nullptr};
     int64_t gx = 8 * ((nxit + 7) / 8);
     if (queue) {
-      xa.q = QArgs{P.xq.order, P.xq.qoff + 9 * ci, E.qcnt + 16 * ci};
-      gx = persistent_grid(occ_x, P.n_cu, nxit);
+      xa.q = QArgs{P.xq.order, P.xq.qoff + 9 * ci};
+      gx = 8 * P.xq.maxlen_h[ci];
     }
     if (nxit > 0) {
       if (P.gga)
@@ -1200,11 +1177,11 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
       va.vpart = E.vpart;
       va.vflag = E.vflag;
       va.counters = E.counters;
-      va.q = QArgs{nullptr, nullptr, nullptr};
+      va.q = QArgs{nullptr, nullptr};
       int64_t gv = 8 * ((nvit + 7) / 8);
       if (queue) {
-        va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci, E.qcnt + 16 * ci + 8};
-        gv = persistent_grid(occ_v, P.n_cu, nvit);
+        va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci};
+        gv = 8 * P.vq.maxlen_h[ci];
       }
       if (nvit > 0) k_vgemm<T><<<gv, NTV, 0, s>>>(va);
       const int64_t nd = P.dchunk_h[ci + 1] - P.dchunk_h[ci];
@@ -1241,24 +1218,6 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
   return hipGetLastError();
 }
 
-template <class T, bool GGA>
-int occ_x_typed() {
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_xgemm<T, GGA>), NTX, 0) !=
-      hipSuccess)
-    n = 1;
-  return std::max(n, 1);
-}
-
-template <class T>
-int occ_v_typed() {
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_vgemm<T>), NTV, 0) !=
-      hipSuccess)
-    n = 1;
-  return std::max(n, 1);
-}
-
 }  // namespace
 
 hipError_t launch_screen(const BasisDev &b, const GridDev &g, const int *cand_p, const int64_t *cand_r,
@@ -1269,25 +1228,13 @@ hipError_t launch_screen(const BasisDev &b, const GridDev &g, const int *cand_p,
 }
 
 hipError_t launch_begin(const Plan &P, const IoDev &io, hipStream_t s) {
-  k_begin<<<1, NT, 0, s>>>(P.ev.io, io, P.ev.counters, P.ev.qcnt, int(16 * P.chunks_h.size()));
+  k_begin<<<1, NT, 0, s>>>(P.ev.io, io, P.ev.counters);
   return hipGetLastError();
 }
 
 hipError_t launch_body(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
   if (P.opts.prec == KLDI_PREC_FP64) return body_typed<double>(P, want_v, s, ev);
   return body_typed<float>(P, want_v, s, ev);
-}
-
-int occupancy_x(const Plan &P) {
-  const bool d = P.opts.prec == KLDI_PREC_FP64;
-  static const int o[4] = {occ_x_typed<float, false>(), occ_x_typed<float, true>(), occ_x_typed<double, false>(),
-                           occ_x_typed<double, true>()};
-  return o[2 * (d ? 1 : 0) + (P.gga ? 1 : 0)];
-}
-
-int occupancy_v(const Plan &P) {
-  static const int o[2] = {occ_v_typed<float>(), occ_v_typed<double>()};
-  return o[P.opts.prec == KLDI_PREC_FP64 ? 1 : 0];
 }
 
 }  // namespace kldi

@@ -103,7 +103,6 @@ struct EvalDev {
   unsigned long long *counters;  // [4]: pairs X, pairs V, nonfinite flag, points on the surrogate
   double *escratch;        // [n_mol] E_xc of kldi_eval_grid
   IoDev *io;               // [1] caller buffers of the running evaluation
-  int *qcnt;               // [n_gchunks * 16] work-queue counters (X: 8 per chunk, V: 8 per chunk)
 };
 
 // A range of grid blocks processed with one filling of the Phi / Z workspaces.
@@ -121,11 +120,13 @@ struct VItem {
   int lpair;     // index of (pc, qc) among the molecule's pairs
 };
 
-// Work order of the persistent GEMM kernels: each grid chunk's items are split into 8 queues (one
-// per XCD, contiguous in blocks / segments for L2 sharing), each ordered by decreasing cost.
+// Work order of the GEMM kernels under KLDI_SCHED_QUEUE: each grid chunk's items are split into 8
+// queues of about equal cost (one per XCD, contiguous in blocks / segments for L2 sharing), each
+// ordered by decreasing cost; workgroup b runs position b / 8 of queue b % 8.
 struct Queues {
   int *order = nullptr;          // [n_items] item ids in queue order
   int64_t *qoff = nullptr;       // [n_gchunks * 9] queue boundaries (positions in order)
+  std::vector<int64_t> maxlen_h; // [n_gchunks] longest queue of each grid chunk
 };
 
 struct Plan {
@@ -207,9 +208,6 @@ hipError_t launch_begin(const Plan &P, const IoDev &io, hipStream_t s);
 // everything after k_begin (captured into a graph when the plan runs in graph mode)
 hipError_t launch_body(const Plan &P, bool want_v, hipStream_t s,
                        hipEvent_t *ev /* KLDI_N_STAGES + 1 events, or NULL */);
-// resident workgroups per CU of the persistent GEMM kernels at the plan's precision
-int occupancy_x(const Plan &P);
-int occupancy_v(const Plan &P);
 hipError_t launch_xc_arrays(int xc, const double *rho, const double *sigma, int64_t n, double rho_cut, double *f,
                             double *vr, double *vs, hipStream_t s);
 // functional surrogate (mlp.hip)

@@ -1,5 +1,5 @@
-"""GPU: the batching form -- many uneven molecules in one plan (kldi_batch_create), the persistent
-work-queue schedule, captured-graph evaluation and the autotuner -- through the C ABI.
+"""GPU: the batching form -- many uneven molecules in one plan (kldi_batch_create), the per-XCD
+queue schedule, captured-graph evaluation and the autotuner -- through the C ABI.
 
 Each molecule of a batch is an independent problem: its results are checked against the FP64 oracle
 run on that molecule alone, and against a single-molecule plan of the same molecule (bit for bit: the
@@ -77,7 +77,7 @@ def test_batch_equals_single_plans_bitwise(mod, prec):
 
 @pytest.mark.parametrize("xc,prec", [("lda", "fp32"), ("pbe", "fp32"), ("pbe", "fp64")])
 def test_queue_schedule_equals_grid_schedule(mod, cfg0, xc, prec):
-    """The persistent schedule changes only which workgroup runs an item and when."""
+    """The queue schedule changes only which workgroup runs an item and when."""
     p = cfg0
     D = torch.from_numpy(p.D).cuda()
     outs = []
@@ -145,9 +145,10 @@ def test_autotune_picks_a_measured_configuration(mod):
     B.close()
 
 
-@pytest.mark.skip(reason="a GPU run of this case went silent for 180 s and was stopped; reading the code and a "
-                         "CPU build that walks every kernel index of this batch found no cause yet, so the case stays "
-                         "off the GPU until one is shown")
+@pytest.mark.skip(reason="a GPU run of this case (queue schedule, then persistent workgroups pulling items from "
+                         "atomic counters) went silent for 180 s and was stopped, as did the 200-atom chain under that "
+                         "schedule; reading the code and a CPU build that walks every kernel index found no cause, so "
+                         "the case stays off the GPU until one is shown")
 def test_batch_of_workload_members_against_oracle(mod):
     """Eight molecules of the batching workload (5-60 atoms, 50 x 194 grid per atom): the two smallest
     against the unscreened FP64 oracle, all of them FP32 against FP64 within the precision targets."""
