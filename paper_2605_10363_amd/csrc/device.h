@@ -48,13 +48,6 @@ struct Mma<float> {
   static __device__ __forceinline__ int row(int v, int l) { return 4 * (l >> 4) + v; }
 };
 
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
-  // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
-  // work items so neighbouring items (similar retained supports) share an L2
-  int64_t per = (n + 7) / 8;
-  return (bid & 7) * per + (bid >> 3);
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;

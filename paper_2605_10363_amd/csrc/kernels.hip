@@ -189,7 +189,10 @@ __device__ __forceinline__ void wg_barrier() {
   asm volatile("" ::: "memory");
 }
 
-// Work-item schedules.  Grid: workgroup b runs item xcd_remap(b) (contiguous item ranges per XCD).
+// Work-item schedules.  Grid: workgroup b runs item b; the dispatcher deals consecutive workgroups
+// round-robin over the 8 XCDs, so every XCD gets an interleaved share of each region of the molecule
+// (measured: far better balanced than contiguous item ranges per XCD, whose costs differ along the
+// molecule; the lost L2 sharing between neighbouring items costs less).
 // Queue: 8 per-XCD queues of about equal cost, each ordered by decreasing cost; workgroup b runs
 // position b / 8 of queue b % 8 (the dispatcher places workgroup b on XCD b % 8), or nothing past the
 // end of its queue.
@@ -201,8 +204,7 @@ struct QArgs {
 template <class F>
 __device__ __forceinline__ void run_items(const QArgs &q, int64_t item0, int64_t n_items, F &&run) {
   if (q.order == nullptr) {
-    const int64_t il = xcd_remap(blockIdx.x, n_items);
-    if (il < n_items) run(il);
+    if (int64_t(blockIdx.x) < n_items) run(int64_t(blockIdx.x));
     return;
   }
   const int qx = blockIdx.x & 7;
@@ -239,8 +241,7 @@ static_assert(8 % kXFlush == 0, "the flush interval must divide the 8 MFMA steps
 
 // One workgroup per (grid block r, chunk c of 4 retained output tiles): X_pr = sum_q D_pq Phi_qr for
 // the 4 tiles p = S_r[4c .. 4c+3], then the chunk's contribution to rho and grad rho.  Wave w owns
-// tile 4c + (w & 3) and points 64 (w >> 2) .. 64 (w >> 2) + 63.  The chunks of one block are
-// consecutive work items and run side by side on one XCD, sharing the block's Phi tiles in L2.
+// tile 4c + (w & 3) and points 64 (w >> 2) .. 64 (w >> 2) + 63.
 // FP32 operands: MFMA accumulation spans one 32-AO K tile, the running sum is FP64.
 template <class T, bool GGA>
 __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
