@@ -232,12 +232,6 @@ struct XArgs {
 
 constexpr int NTX = 512;   // threads per X workgroup: 8 waves, each 32 rows x 64 points
 
-// FP32 operands: MFMA steps (K = 4 each) accumulated in FP32 before the FP64 running sum takes them
-#ifndef KLDI_XFLUSH
-#define KLDI_XFLUSH 8
-#endif
-constexpr int kXFlush = KLDI_XFLUSH;
-static_assert(8 % kXFlush == 0, "the flush interval must divide the 8 MFMA steps of a K tile");
 
 // One workgroup per (grid block r, chunk c of 4 retained output tiles): X_pr = sum_q D_pq Phi_qr for
 // the 4 tiles p = S_r[4c .. 4c+3], then the chunk's contribution to rho and grad rho.  Wave w owns
@@ -259,6 +253,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   __shared__ __align__(16) unsigned char s_raw[kStageBytes];
   __shared__ int s_p[kMaxNp];
   __shared__ int s_list[kMaxNp];
+  __shared__ int s_q[kMaxNp];      // q of each compacted entry (FP32 path)
   __shared__ int s_w[8];
   __shared__ double s_acc[4][4][kG];
   run_items(A.q, A.item0, A.n_items, [&](int64_t il) {
@@ -310,6 +305,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
     }
     if (mask) {
       s_list[pos] = t | (mask << 16);
+      s_q[pos] = s_p[t];
       pairs += __popc(mask);
     }
     n_list = tot;
@@ -341,21 +337,22 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
     const int m16 = l & 15, g = l >> 4;
     const float *Df = reinterpret_cast<const float *>(Dt);
     const float *Pf = reinterpret_cast<const float *>(phi);
+    // D tile row of this wave's chunk entry (waves 0-3): an entry past the end of S_r uses entry np - 1
+    // (valid memory, never multiplied: its wave has no executable pair)
+    const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + (ws & 3), np - 1)]);
+    const float *Drow = Df + dtile(pa, mo.tile0) * (kD * kD);
     auto issue = [&](int e) {
-      const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
       float *dst = ring + (e & (kRing - 1)) * kSlotF + ws * 1024;   // this wave's 4 KB of the slot
       if (ws < 4) {
-        // D tile (p, q) of chunk entry ws; an entry past the end of S_r loads entry np - 1 (valid
-        // memory, never multiplied: its wave has no executable pair)
-        const int q = __builtin_amdgcn_readfirstlane(s_p[t]);
-        const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + ws, np - 1)]);
-        const float *src = Df + dtile(pa, q) * (kD * kD);
+        const int q = __builtin_amdgcn_readfirstlane(s_q[e]);
+        const float *src = Drow + size_t(q - mo.tile0) * (kD * kD);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
           dma16(src + i * kD + 4 * cu, dst + 256 * m);
         }
       } else {
+        const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
         const float *src = Pf + size_t(k0 + t) * (kD * kG) + 1024 * (ws - 4);
 #pragma unroll
         for (int m = 0; m < 4; ++m) dma16(src + 4 * (64 * m + l), dst + 256 * m);
@@ -377,38 +374,45 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
       for (int kk = 0; kk < 8; ++kk)
         F.b[kk] = *reinterpret_cast<const f4 *>(sl + 4 * kD * kD + (8 * g + kk) * kG + 64 * h + 4 * m16);
     };
+    // the FP32 accumulators of sub-tile row ti are added to the FP64 sums every 8 MFMA steps (one K
+    // tile), row 0 after step 3 and row 1 after step 7 of each K tile, so the conversion and FP64 adds
+    // of one row overlap the MFMAs of the other
+    auto flush = [&](int ti) {
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
+        acc[ti][tj] = acc_t{};
+      }
+    };
+    auto mfma_steps = [&](const Frag &F, int k0s, int k1s) {
+#pragma unroll
+      for (int kk = k0s; kk < k1s; ++kk) {
+        const float a0 = F.a[0][kk >> 2][kk & 3], a1 = F.a[1][kk >> 2][kk & 3];
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) {
+          acc[0][tj] = M::mma(a0, F.b[kk][tj], acc[0][tj]);
+          acc[1][tj] = M::mma(a1, F.b[kk][tj], acc[1][tj]);
+        }
+      }
+    };
     for (int j = 0; j < kRing - 1 && j < n_list; ++j) issue(j);
     // step e: wait until this wave's copies of step e have landed (later steps may stay in flight) and
-    // its reads of step e - 1 are done; after the barrier the slot of step e - 1 is free for step
-    // e + kRing - 1
+    // its reads of step e - 1 are done; after the barrier the slot of step e - 1 takes step
+    // e + kRing - 1.  (Measured: issuing these copies between the two halves of the MFMA steps, or
+    // reading the next step's fragments during this step's MFMAs, is slower.)
     for (int e = 0; e < n_list; ++e) {
       const int ahead = min(n_list, e + kRing - 1) - (e + 1);
       if (ahead >= 2) wait_vm_lds<8>(); else if (ahead == 1) wait_vm_lds<4>(); else wait_vm_lds<0>();
       wg_barrier();
       if (e + kRing - 1 < n_list) issue(e + kRing - 1);
-      const int mask = __builtin_amdgcn_readfirstlane(s_list[e] >> 16);
-      if ((mask >> us) & 1) {
+      if ((__builtin_amdgcn_readfirstlane(s_list[e] >> 16) >> us) & 1) {
         Frag F;
         frag(e, F);
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-          const float a0 = F.a[0][kk >> 2][kk & 3], a1 = F.a[1][kk >> 2][kk & 3];
-#pragma unroll
-          for (int tj = 0; tj < 4; ++tj) {
-            acc[0][tj] = M::mma(a0, F.b[kk][tj], acc[0][tj]);
-            acc[1][tj] = M::mma(a1, F.b[kk][tj], acc[1][tj]);
-          }
-          if (kk % kXFlush == kXFlush - 1) {
-#pragma unroll
-            for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-              for (int tj = 0; tj < 4; ++tj) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
-                acc[ti][tj] = acc_t{};
-              }
-          }
-        }
+        mfma_steps(F, 0, 4);
+        flush(0);
+        mfma_steps(F, 4, 8);
+        flush(1);
       }
     }
     __syncthreads();
