@@ -79,10 +79,8 @@ __device__ __forceinline__ int block_scan(int flag, int *s_w, int *total) {
 // ------------------------------------------------------------------------------------------------
 // Basis functions (contracted cartesian Gaussians, N_rel-normalised components)
 // ------------------------------------------------------------------------------------------------
-static __constant__ int c_pow[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
-                                 {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
-static __constant__ double c_nrel[10] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.7320508075688772, 1.7320508075688772,
-                                  1.0, 1.7320508075688772, 1.0};
+// Cartesian components in AO order: s; x y z; xx xy xz yy yz zz.  N_rel = sqrt(3) for xy, xz, yz, else 1.
+constexpr double kSqrt3 = 1.7320508075688772;
 
 __device__ __forceinline__ void pw4(double d, double *p) {
   p[0] = 1.0;
@@ -115,24 +113,33 @@ __device__ __forceinline__ void for_tile_aos(const BasisDev &B, int p, double x,
       if (GRAD) R1 -= 2.0 * pexp[k] * e;
     }
     const int l = sh_l[s], ao0 = sh_ao0[s];
-    const int cb = (l == 0) ? 0 : (l == 1 ? 1 : 4), nc = (l + 1) * (l + 2) / 2;
-    double px[4], py[4], pz[4];
-    pw4(dx, px);
-    pw4(dy, py);
-    pw4(dz, pz);
-    for (int c = 0; c < nc; ++c) {
+    // component c of the shell: angular factor A (N_rel included) and its derivatives; value A R,
+    // gradient dA R + A (dx, dy, dz) R1, in AO order.
+    auto put = [&](int c, double A, double ax, double ay, double az) {
       const int ao = ao0 + c;
-      if (ao < a_lo || ao >= a_hi) continue;
-      const int lx = c_pow[cb + c][0], ly = c_pow[cb + c][1], lz = c_pow[cb + c][2];
-      const double nr = c_nrel[cb + c];
-      const double ang = px[lx] * py[ly] * pz[lz];
+      if (ao < a_lo || ao >= a_hi) return;
       double gx = 0, gy = 0, gz = 0;
       if (GRAD) {
-        gx = nr * ((lx ? lx * px[lx - 1] * py[ly] * pz[lz] : 0.0) * R + ang * dx * R1);
-        gy = nr * ((ly ? ly * px[lx] * py[ly - 1] * pz[lz] : 0.0) * R + ang * dy * R1);
-        gz = nr * ((lz ? lz * px[lx] * py[ly] * pz[lz - 1] : 0.0) * R + ang * dz * R1);
+        gx = ax * R + A * dx * R1;
+        gy = ay * R + A * dy * R1;
+        gz = az * R + A * dz * R1;
       }
-      emit(ao - a_lo, nr * ang * R, gx, gy, gz);
+      emit(ao - a_lo, A * R, gx, gy, gz);
+    };
+    if (l == 0) {
+      put(0, 1.0, 0.0, 0.0, 0.0);
+    } else if (l == 1) {
+      put(0, dx, 1.0, 0.0, 0.0);
+      put(1, dy, 0.0, 1.0, 0.0);
+      put(2, dz, 0.0, 0.0, 1.0);
+    } else {
+      const double r3 = kSqrt3;
+      put(0, dx * dx, 2.0 * dx, 0.0, 0.0);
+      put(1, r3 * dx * dy, r3 * dy, r3 * dx, 0.0);
+      put(2, r3 * dx * dz, r3 * dz, 0.0, r3 * dx);
+      put(3, dy * dy, 0.0, 2.0 * dy, 0.0);
+      put(4, r3 * dy * dz, 0.0, r3 * dz, r3 * dy);
+      put(5, dz * dz, 0.0, 0.0, 2.0 * dz);
     }
   }
 }
@@ -153,7 +160,7 @@ __device__ __forceinline__ void eval_ao(const BasisDev &B, int ao, double x, dou
   }
   const int cp = B.ao_comp[ao];
   const int lx = cp & 3, ly = (cp >> 2) & 3, lz = (cp >> 4) & 3;
-  const double nr = ((lx == 1) + (ly == 1) + (lz == 1) == 2) ? 1.7320508075688772 : 1.0;
+  const double nr = ((lx == 1) + (ly == 1) + (lz == 1) == 2) ? kSqrt3 : 1.0;
   double px[4], py[4], pz[4];
   pw4(dx, px);
   pw4(dy, py);
