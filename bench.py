@@ -29,6 +29,15 @@ GOLDEN_BLOCKED = os.path.join(ROOT, "tests", "golden", "cfg1_blocked.json")   # 
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+def kernels_sha1():
+    """SHA-1 of the device sources (kernels, their device helpers and shared structs): the HBM counters
+    in profiles/traffic.json describe the kernels built from exactly these files."""
+    h = hashlib.sha1()
+    for f in ("kernels.hip", "device.h", "kldi_impl.h"):
+        h.update(open(os.path.join(ROOT, "paper_2605_10363_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -37,7 +46,6 @@ def time_path(plan, D, steps, warmup, torch):
     for _ in range(warmup):
         plan.eval(D)
     torch.cuda.synchronize()
-    st = plan.check()
     plan.timing(True)
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -51,6 +59,7 @@ def time_path(plan, D, steps, warmup, torch):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     stage, n = plan.stage_ms()
+    st = plan.check()                      # counters of the last evaluation
     plan.timing(False)
     rho, exc, vxc = outs
     return ms, stage, st, float(exc.item()), vxc.cpu().numpy(), rho
@@ -381,8 +390,7 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC):
         t = json.load(open(TRAFFIC))
-        src = open(os.path.join(ROOT, "paper_2605_10363_amd", "csrc", "kernels.hip"), "rb").read()
-        if t.get("kernels_sha1") == hashlib.sha1(src).hexdigest() and dom in t.get("bytes_per_launch", {}):
+        if t.get("kernels_sha1") == kernels_sha1() and dom in t.get("bytes_per_launch", {}):
             traffic = t["bytes_per_launch"][dom]
     out["roofline"] = {"bound": "mfma", "kernel": "k_" + dom, "achieved": round(achieved, 3),
                        "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4),

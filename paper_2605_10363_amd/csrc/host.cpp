@@ -419,6 +419,21 @@ int64_t count_v_items(const Plan &P, const std::vector<std::vector<int>> &blk_ch
   return n;
 }
 
+// Deal groups of consecutive items (group_start; the last ends at i1) round-robin over 8 queues, group g
+// to queue g % 8, each queue keeping its groups' items in order.  Appends to order and writes 9
+// boundaries to qoff.
+void make_rr_queues(int64_t i1, const std::vector<int64_t> &group_start, std::vector<int> &order, int64_t *qoff) {
+  const size_t ng = group_start.size();
+  for (int x = 0; x < 8; ++x) {
+    qoff[x] = int64_t(order.size());
+    for (size_t g = size_t(x); g < ng; g += 8) {
+      const int64_t e = (g + 1 < ng) ? group_start[g + 1] : i1;
+      for (int64_t it = group_start[g]; it < e; ++it) order.push_back(int(it));
+    }
+  }
+  qoff[8] = int64_t(order.size());
+}
+
 // Split items [i0, i1) -- groups of consecutive items given by group_end -- into 8 contiguous ranges
 // of about equal cost, then order each range by decreasing group cost (items of a group stay
 // together, in their order).  Appends to order and writes 9 boundaries to qoff.
@@ -571,7 +586,7 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
     max_vm = std::max(max_vm, P.vmoff_h[C.blk1] - P.vmoff_h[C.blk0]);
   }
 
-  // per-XCD queue orders, per grid chunk
+  // per-XCD item orders of the schedule, per grid chunk
   const size_t nch = P.chunks_h.size();
   {
     // Vxc items of diagonal chunk pairs, per grid chunk (their diagonal tiles run in FP64)
@@ -597,6 +612,17 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
         gs.push_back(P.blk_item_off_h[r]);
         const double np = double(P.blk_off_h[r + 1] - P.blk_off_h[r]);
         gc.push_back(double(P.blk_item_off_h[r + 1] - P.blk_item_off_h[r]) * (np + 4.0));
+      }
+      if (schedule == KLDI_SCHED_GRID) {
+        // grid blocks (X) and Vxc segments (V) dealt round-robin over the XCDs: the items of a block or
+        // segment share its Phi / Z tiles in one L2, and every XCD gets an interleaved share of the
+        // molecule (its cost varies along the molecule)
+        make_rr_queues(C.xit1, gs, xorder, &xqoff[9 * ci]);
+        std::vector<int64_t> vs;
+        for (int64_t it = C.vit0; it < C.vit1; ++it)
+          if (it == C.vit0 || P.items_h[it].r0 != P.items_h[it - 1].r0) vs.push_back(it);
+        make_rr_queues(C.vit1, vs, vorder, &vqoff[9 * ci]);
+        continue;
       }
       make_queues(C.xit0, C.xit1, gs, gc, xorder, &xqoff[9 * ci]);
       // V: one group per item, cost ~ candidate tile pairs over its segment

@@ -189,24 +189,19 @@ __device__ __forceinline__ void wg_barrier() {
   asm volatile("" ::: "memory");
 }
 
-// Work-item schedules.  Grid: workgroup b runs item b; the dispatcher deals consecutive workgroups
-// round-robin over the 8 XCDs, so every XCD gets an interleaved share of each region of the molecule
-// (measured: far better balanced than contiguous item ranges per XCD, whose costs differ along the
-// molecule; the lost L2 sharing between neighbouring items costs less).
-// Queue: 8 per-XCD queues of about equal cost, each ordered by decreasing cost; workgroup b runs
-// position b / 8 of queue b % 8 (the dispatcher places workgroup b on XCD b % 8), or nothing past the
-// end of its queue.
+// Work-item schedules: 8 per-XCD queues of items (host-built, see kldi_schedule); workgroup b runs
+// position b / 8 of queue b % 8 -- the dispatcher places workgroup b on XCD b % 8 -- or nothing past
+// the end of its queue.  Grid: grid blocks / Vxc segments dealt round-robin over the queues (measured:
+// contiguous item ranges per XCD leave most XCDs idle while the densest region of the molecule
+// finishes).  Queue: contiguous ranges of about equal estimated cost, each ordered by decreasing cost.
 struct QArgs {
-  const int *order;        // item ids in queue order (NULL: grid schedule)
+  const int *order;        // item ids in queue order
   const int64_t *qoff;     // [9] queue boundaries of this launch
 };
 
 template <class F>
 __device__ __forceinline__ void run_items(const QArgs &q, int64_t item0, int64_t n_items, F &&run) {
-  if (q.order == nullptr) {
-    if (int64_t(blockIdx.x) < n_items) run(int64_t(blockIdx.x));
-    return;
-  }
+  (void)n_items;
   const int qx = blockIdx.x & 7;
   const int64_t pos = q.qoff[qx] + (blockIdx.x >> 3);
   if (pos < q.qoff[qx + 1]) run(int64_t(q.order[pos]) - item0);
@@ -1073,7 +1068,6 @@ __global__ __launch_bounds__(NT) void k_esum(const MolDev *mol, const double *__
 template <class T>
 hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
   const EvalDev &E = P.ev;
-  const bool queue = P.schedule == KLDI_SCHED_QUEUE;
   // stage events: per stage when the grid is processed in one chunk; with several chunks the
   // stages interleave and everything between the D preparation and the final sums is one stage
   const bool one = P.chunks_h.size() == 1;
@@ -1110,12 +1104,8 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
     xa.counters = E.counters;
     xa.t_b = P.opts.t_b;
     xa.t_d = P.opts.t_d;
-    xa.q = QArgs{nullptr, nullptr};
-    int64_t gx = 8 * ((nxit + 7) / 8);
-    if (queue) {
-      xa.q = QArgs{P.xq.order, P.xq.qoff + 9 * ci};
-      gx = 8 * P.xq.maxlen_h[ci];
-    }
+    xa.q = QArgs{P.xq.order, P.xq.qoff + 9 * ci};
+    const int64_t gx = 8 * P.xq.maxlen_h[ci];
     if (nxit > 0) {
       if (P.gga)
         k_xgemm<T, true><<<gx, NTX, 0, s>>>(xa);
@@ -1182,12 +1172,8 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
       va.vpart = E.vpart;
       va.vflag = E.vflag;
       va.counters = E.counters;
-      va.q = QArgs{nullptr, nullptr};
-      int64_t gv = 8 * ((nvit + 7) / 8);
-      if (queue) {
-        va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci};
-        gv = 8 * P.vq.maxlen_h[ci];
-      }
+      va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci};
+      const int64_t gv = 8 * P.vq.maxlen_h[ci];
       if (nvit > 0) k_vgemm<T><<<gv, NTV, 0, s>>>(va);
       const int64_t nd = P.dchunk_h[ci + 1] - P.dchunk_h[ci];
       if (sizeof(T) == 4 && nd > 0) {
