@@ -238,9 +238,9 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   typedef typename M::acc_t acc_t;
   constexpr int E = Units<T>::E;
   constexpr bool F32 = sizeof(T) == 4;
-  // FP32: a ring of kRing LDS slots of one K step each (4 D tiles + one Phi tile, 32 KB).  FP64: one
-  // padded stage filled through registers.
-  constexpr int kRing = 4, kSlotF = 4 * kD * kD + kD * kG;
+  // FP32: a ring of kRing LDS slots of one K step each; a step takes kPer compacted entries, each 4 D
+  // tiles + one Phi tile (32 KB).  FP64: one padded stage filled through registers.
+  constexpr int kRing = 2, kPer = 2, kEntF = 4 * kD * kD + kD * kG, kSlotF = kPer * kEntF;
   constexpr int LDA_S = lda_s<T>(), LDB_S = ldb_s<T>();
   constexpr int kA = 128 * LDA_S, kB = 32 * LDB_S;
   constexpr int kXsBytes = 4 * kD * kG * 8;   // the epilogue's X (FP64, 4 tiles) overlays the staging area
@@ -321,12 +321,13 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
     }
   const bool has_u = 4 * c + u < np;
   if constexpr (F32) {
-    // ---- FP32 operands.  Slot e % kRing holds step e: the 4 D tiles (p_u, q) as [row i][k] with the
-    // 16-byte units of row i XOR-swizzled (unit c at c ^ (i & 7)), then Phi_q as [k][point].  The copies
-    // go global -> LDS directly, kRing - 1 steps ahead; one barrier per step.  Index maps of the MFMA steps:
-    // step kk of a wave takes k = 8 (l / 16) + kk, so a lane reads the 8 values of its row of D with two
-    // 16-byte loads, and output column c of sub-tile tj is point 64 h + 4 c + tj, so a lane reads its 4
-    // values of a row of Phi_q with one 16-byte load.
+    // ---- FP32 operands.  Slot S % kRing holds K step S: entries kPer S .. kPer S + kPer - 1 of the
+    // compacted list, each the 4 D tiles (p_u, q) as [row i][k] with the 16-byte units of row i
+    // XOR-swizzled (unit c at c ^ (i & 7)), then Phi_q as [k][point].  The copies go global -> LDS
+    // directly, one step ahead; one barrier per step.  Index maps of the MFMA steps: step kk of a wave
+    // takes k = 8 (l / 16) + kk, so a lane reads the 8 values of its row of D with two 16-byte loads,
+    // and output column c of sub-tile tj is point 64 h + 4 c + tj, so a lane reads its 4 values of a
+    // row of Phi_q with one 16-byte load.
     float *ring = reinterpret_cast<float *>(s_raw);
     const int ws = __builtin_amdgcn_readfirstlane(w), us = ws & 3;
     const int m16 = l & 15, g = l >> 4;
@@ -336,42 +337,49 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
     // (valid memory, never multiplied: its wave has no executable pair)
     const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + (ws & 3), np - 1)]);
     const float *Drow = Df + dtile(pa, mo.tile0) * (kD * kD);
-    auto issue = [&](int e) {
-      float *dst = ring + (e & (kRing - 1)) * kSlotF + ws * 1024;   // this wave's 4 KB of the slot
-      if (ws < 4) {
-        const int q = __builtin_amdgcn_readfirstlane(s_q[e]);
-        const float *src = Drow + size_t(q - mo.tile0) * (kD * kD);
+    const int n_step = (n_list + kPer - 1) / kPer;
+    // every wave copies 4 KB of each entry of step S (the entries past the list's end repeat its last
+    // entry, so every step issues 4 kPer copies per wave)
+    auto issue = [&](int S) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
-          dma16(src + i * kD + 4 * cu, dst + 256 * m);
+      for (int j = 0; j < kPer; ++j) {
+        const int e = min(kPer * S + j, n_list - 1);
+        float *dst = ring + (S & (kRing - 1)) * kSlotF + j * kEntF + ws * 1024;
+        if (ws < 4) {
+          const int q = __builtin_amdgcn_readfirstlane(s_q[e]);
+          const float *src = Drow + size_t(q - mo.tile0) * (kD * kD);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+            dma16(src + i * kD + 4 * cu, dst + 256 * m);
+          }
+        } else {
+          const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
+          const float *src = Pf + size_t(k0 + t) * (kD * kG) + 1024 * (ws - 4);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) dma16(src + 4 * (64 * m + l), dst + 256 * m);
         }
-      } else {
-        const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
-        const float *src = Pf + size_t(k0 + t) * (kD * kG) + 1024 * (ws - 4);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) dma16(src + 4 * (64 * m + l), dst + 256 * m);
       }
     };
     struct Frag {
       f4 a[2][2];   // rows 16 ti + l % 16 of tile u, k = 8 (l / 16) + 4 hh .. + 3
       f4 b[8];      // row k = 8 (l / 16) + kk of Phi_q, points 64 h + 4 (l % 16) .. + 3
     };
-    auto frag = [&](int e, Frag &F) {
-      const float *sl = ring + (e & (kRing - 1)) * kSlotF;
+    auto frag = [&](const float *se, Frag &F) {
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
-          F.a[ti][hh] = *reinterpret_cast<const f4 *>(sl + us * (kD * kD) + (16 * ti + m16) * kD +
+          F.a[ti][hh] = *reinterpret_cast<const f4 *>(se + us * (kD * kD) + (16 * ti + m16) * kD +
                                                       4 * ((2 * g + hh) ^ (m16 & 7)));
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk)
-        F.b[kk] = *reinterpret_cast<const f4 *>(sl + 4 * kD * kD + (8 * g + kk) * kG + 64 * h + 4 * m16);
+        F.b[kk] = *reinterpret_cast<const f4 *>(se + 4 * kD * kD + (8 * g + kk) * kG + 64 * h + 4 * m16);
     };
     // the FP32 accumulators of sub-tile row ti are added to the FP64 sums every 8 MFMA steps (one K
     // tile), row 0 after step 3 and row 1 after step 7 of each K tile, so the conversion and FP64 adds
-    // of one row overlap the MFMAs of the other
+    // of one row overlap the MFMAs of the other.  (Measured at the 200-atom chain: flushing after every
+    // second K tile saves 4% of this kernel but raises the E_xc error sevenfold.)
     auto flush = [&](int ti) {
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) {
@@ -391,23 +399,26 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
         }
       }
     };
-    for (int j = 0; j < kRing - 1 && j < n_list; ++j) issue(j);
-    // step e: wait until this wave's copies of step e have landed (later steps may stay in flight) and
-    // its reads of step e - 1 are done; after the barrier the slot of step e - 1 takes step
-    // e + kRing - 1.  (Measured: issuing these copies between the two halves of the MFMA steps, or
-    // reading the next step's fragments during this step's MFMAs, is slower.)
-    for (int e = 0; e < n_list; ++e) {
-      const int ahead = min(n_list, e + kRing - 1) - (e + 1);
-      if (ahead >= 2) wait_vm_lds<8>(); else if (ahead == 1) wait_vm_lds<4>(); else wait_vm_lds<0>();
+    static_assert(kRing == 2, "the waits below assume one step in flight");
+    if (n_step > 0) issue(0);
+    // step S: wait until this wave's copies of step S have landed and its reads of step S - 1 are done;
+    // after the barrier the slot of step S - 1 takes step S + 1.  (Measured: issuing the copies
+    // between MFMA steps, or reading the next step's fragments during this step's MFMAs, is slower.)
+    for (int S = 0; S < n_step; ++S) {
+      wait_vm_lds<0>();
       wg_barrier();
-      if (e + kRing - 1 < n_list) issue(e + kRing - 1);
-      if ((__builtin_amdgcn_readfirstlane(s_list[e] >> 16) >> us) & 1) {
-        Frag F;
-        frag(e, F);
-        mfma_steps(F, 0, 4);
-        flush(0);
-        mfma_steps(F, 4, 8);
-        flush(1);
+      if (S + 1 < n_step) issue(S + 1);
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int e = kPer * S + j;
+        if (e < n_list && ((__builtin_amdgcn_readfirstlane(s_list[e] >> 16) >> us) & 1)) {
+          Frag F;
+          frag(ring + (S & (kRing - 1)) * kSlotF + j * kEntF, F);
+          mfma_steps(F, 0, 4);
+          flush(0);
+          mfma_steps(F, 4, 8);
+          flush(1);
+        }
       }
     }
     __syncthreads();
