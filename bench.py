@@ -123,7 +123,8 @@ def cpu_baseline_batch(ps, n_mol_sample=8, pts_per_mol=20000, seed=0):
 
 
 def bench_batch(args, torch):
-    """The batching form: 256 uneven molecules in one plan, autotuned, replayed as a captured graph."""
+    """The batching form: 256 uneven molecules in one plan, replayed as a captured graph; the schedule and
+    Vxc segment length are the autotuner's (--schedule auto) or given."""
     import synth
     from paper_2605_10363_amd.plan import Batch
     t0 = time.time()
@@ -132,10 +133,15 @@ def bench_batch(args, torch):
         len(ps), sum(p.n_atoms for p in ps), sum(p.n_ao for p in ps), sum(p.n_points for p in ps), time.time() - t0))
     res = {}
     for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
-        B = Batch(ps, xc=args.xc, prec=prec)
+        B = Batch(ps, xc=args.xc, prec=prec, v_segment=args.v_segment,
+                  schedule="grid" if args.schedule == "auto" else args.schedule)
         info = B.info()
         D = B.pack([p.D for p in ps])
-        tune = B.autotune(D, reps=2)
+        if args.schedule == "auto":
+            tune = B.autotune(D, reps=2)
+        else:
+            inf = B.info()
+            tune = {"v_segment": inf["v_segment"], "schedule": inf["schedule"], "ms": None, "n_tried": 0}
         B.graph(True)
         log("%s batch plan: %.0f ms, retained fraction %.4f, %d X items, %d V items, %.1f GB; autotune %s" % (
             prec, info["plan_ms"], info["retained_fraction"], info["n_x_items"], info["n_v_items"],
