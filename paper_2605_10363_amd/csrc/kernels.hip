@@ -191,9 +191,10 @@ __device__ __forceinline__ void wg_barrier() {
 
 // Work-item schedules: 8 per-XCD queues of items (host-built, see kldi_schedule); workgroup b runs
 // position b / 8 of queue b % 8 -- the dispatcher places workgroup b on XCD b % 8 -- or nothing past
-// the end of its queue.  Grid: grid blocks / Vxc segments dealt round-robin over the queues (measured:
-// contiguous item ranges per XCD leave most XCDs idle while the densest region of the molecule
-// finishes).  Queue: contiguous ranges of about equal estimated cost, each ordered by decreasing cost.
+// the end of its queue.  Grid: grid blocks / Vxc segments dealt round-robin over the queues, the Vxc
+// queues ordered by decreasing cost (measured: contiguous item ranges per XCD leave most XCDs idle while
+// the densest region of the molecule finishes).  Queue: contiguous ranges of about equal estimated cost,
+// each ordered by decreasing cost.
 struct QArgs {
   const int *order;        // item ids in queue order
   const int64_t *qoff;     // [9] queue boundaries of this launch

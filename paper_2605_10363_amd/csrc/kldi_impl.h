@@ -122,8 +122,8 @@ struct VItem {
 
 // Work order of the GEMM kernels: each grid chunk's items in 8 queues, one per XCD; workgroup b runs
 // position b / 8 of queue b % 8.  KLDI_SCHED_GRID deals grid blocks / Vxc segments round-robin over the
-// queues; KLDI_SCHED_QUEUE cuts contiguous ranges of about equal estimated cost, each ordered by
-// decreasing cost.
+// queues (Vxc queues in decreasing estimated cost); KLDI_SCHED_QUEUE cuts contiguous ranges of about
+// equal estimated cost, each ordered by decreasing cost.
 struct Queues {
   int *order = nullptr;          // [n_items] item ids in queue order
   int64_t *qoff = nullptr;       // [n_gchunks * 9] queue boundaries (positions in order)
