@@ -996,20 +996,38 @@ __global__ __launch_bounds__(NT) void k_vdiag(VDArgs A) {
     if (!((mask >> (5 * w)) & 1)) continue;      // bit 4 w + w: the pair (p, p)
     const int ci = A.cinfo[A.cioff[r] + it.pc];
     const size_t t = size_t(A.st.blk_off[r] + tile_pos(ci, w) - A.ret0) * (kD * kG);
-    const float *ph = A.phi + t;
-    const unsigned short *pl = A.phil + t;
-    const float *zt = A.zws + t;
-    const int i0 = l & 15;
-    for (int kk = 0; kk < kG / 4; ++kk) {
-      const int kc = 4 * kk + (l >> 4);
-      const double a0 = double(ph[i0 * kG + kc]) + from_bf16(pl[i0 * kG + kc]);
-      const double a1 = double(ph[(i0 + 16) * kG + kc]) + from_bf16(pl[(i0 + 16) * kG + kc]);
-      const double b0 = double(zt[i0 * kG + kc]);
-      const double b1 = double(zt[(i0 + 16) * kG + kc]);
-      dd[0][0] = Mma<double>::mma(a0, b0, dd[0][0]);
-      dd[0][1] = Mma<double>::mma(a0, b1, dd[0][1]);
-      dd[1][0] = Mma<double>::mma(a1, b0, dd[1][0]);
-      dd[1][1] = Mma<double>::mma(a1, b1, dd[1][1]);
+    // MFMA step kk of lane group g = l / 16 takes point 32 g + kk, so a lane reads 8 consecutive points
+    // of each of its two rows (i0, i0 + 16) with 16-byte loads per 8 steps
+    const int i0 = l & 15, g = l >> 4;
+    const float *ph = A.phi + t + i0 * kG + 32 * g;
+    const unsigned short *pl = A.phil + t + i0 * kG + 32 * g;
+    const float *zt = A.zws + t + i0 * kG + 32 * g;
+    for (int c8 = 0; c8 < 4; ++c8) {
+      f4 h[2][2], z[2][2];
+      uint4 lo[2];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) {
+        const int o = ti * 16 * kG + 8 * c8;
+        h[ti][0] = *reinterpret_cast<const f4 *>(ph + o);
+        h[ti][1] = *reinterpret_cast<const f4 *>(ph + o + 4);
+        z[ti][0] = *reinterpret_cast<const f4 *>(zt + o);
+        z[ti][1] = *reinterpret_cast<const f4 *>(zt + o + 4);
+        lo[ti] = *reinterpret_cast<const uint4 *>(pl + o);
+      }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        double a[2], bz[2];
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti) {
+          const unsigned w32 = (&lo[ti].x)[kk >> 1];
+          a[ti] = double(h[ti][kk >> 2][kk & 3]) + from_bf16((unsigned short)((kk & 1) ? (w32 >> 16) : (w32 & 0xffff)));
+          bz[ti] = double(z[ti][kk >> 2][kk & 3]);
+        }
+        dd[0][0] = Mma<double>::mma(a[0], bz[0], dd[0][0]);
+        dd[0][1] = Mma<double>::mma(a[0], bz[1], dd[0][1]);
+        dd[1][0] = Mma<double>::mma(a[1], bz[0], dd[1][0]);
+        dd[1][1] = Mma<double>::mma(a[1], bz[1], dd[1][1]);
+      }
     }
   }
   double *out = A.vpart + size_t(item) * (128 * 128);
