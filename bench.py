@@ -29,6 +29,16 @@ GOLDEN_BLOCKED = os.path.join(ROOT, "tests", "golden", "cfg1_blocked.json")   # 
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+WORKLOADS = {
+    0: "12-atom molecule, 100 cartesian AOs, 52,800 points (40x110 per atom), 128-point blocks, 32-AO tiles, "
+       "LDA, t_b=t_d=1e-10",
+    1: "200-atom chain, 2000 cartesian AOs (3s2p1d/2s1p), 4.53M points (75x302 per atom), 128-point blocks, "
+       "32-AO tiles, PBE, t_b=t_d=1e-10",
+    2: "1000-atom cluster, 10,000 cartesian AOs, 22.65M points (75x302 per atom), 128-point blocks, 32-AO tiles, "
+       "PBE, t_b=t_d=1e-10",
+}
+
+
 def kernels_sha1():
     """SHA-1 of the device sources (kernels, their device helpers and shared structs): the HBM counters
     in profiles/traffic.json describe the kernels built from exactly these files."""
@@ -359,8 +369,7 @@ def main():
         "metric": METRIC, "value": round(mix["ms"], 4), "unit": "ms/eval", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(mix["ms"], 4), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "200-atom chain, 2000 cartesian AOs (3s2p1d/2s1p), 4.53M points (75x302 per atom), "
-                               "128-point blocks, 32-AO tiles, PBE, t_b=t_d=1e-10",
+        "config": {"workload": WORKLOADS.get(args.config, "config %d" % args.config),
                    "path": "mixed: FP32 MFMA block GEMMs, FP64 functional and accumulation",
                    "seeds": p.meta.get("seeds")},
         "tflops": round(flops / (mix["ms"] * 1e-3) / 1e12, 3),
