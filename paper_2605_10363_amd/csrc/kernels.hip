@@ -717,9 +717,9 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   // whose FP32 rounding, correlated over the points of one radial shell where Phi takes one value,
   // would dominate the error of the mixed path.
   constexpr bool F32 = sizeof(T) == 4;
-  // FP32: a ring of kRing LDS slots, one 32-point sub-step each (4 Phi slabs + 4 Z slabs of 32 x 32,
-  // 32 KB).  FP64: two padded stages filled through registers.
-  constexpr int kRing = 4, kSlab = kD * kD, kSlotF = 8 * kSlab;
+  // FP32: a ring of kRing LDS slots, one kSP-point sub-step each (4 Phi slabs + 4 Z slabs of 32 x kSP,
+  // 64 KB).  FP64: two padded stages filled through registers.
+  constexpr int kRing = 2, kSP = 64, kNS = kG / kSP, kSlab = kD * kSP, kSlotF = 8 * kSlab;
   constexpr int kStageBytes = F32 ? kRing * kSlotF * 4 : 4 * kS * int(sizeof(T));
   __shared__ __align__(16) unsigned char s_raw[kStageBytes];
   T *sA = reinterpret_cast<T *>(s_raw);    // FP64: [2][kS]
@@ -782,73 +782,75 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
     any |= tot;
 
     if constexpr (F32) {
-      // sub-step st = 4 e + sub: entry e of the compacted list, points 32 sub .. 32 sub + 31.  Slot st %
-      // kRing: slab a < 4 is Phi_(4pc+a) and slab 4 + b is Z_(4qc+b), each [row i][point] with the
-      // 16-byte units of row i XOR-swizzled (unit c at c ^ (i & 7)); wave w copies slab w, global ->
-      // LDS directly, kRing - 1 sub-steps ahead, and only where the slab's tile has an executable pair.
-      // MFMA step kk takes point 8 (l / 16) + kk of the sub-step, so a lane reads the 8 values of its
-      // row of a slab with two 16-byte loads.
+      // sub-step st = kNS e + sub: entry e of the compacted list, points kSP sub .. kSP sub + kSP - 1.  Slot
+      // st % kRing: slab a < 4 is Phi_(4pc+a) and slab 4 + b is Z_(4qc+b), each [row i][point] with the
+      // 16-byte units of row i XOR-swizzled within groups of 8 (unit c at c ^ (i & 7)); wave w copies slab
+      // w, global -> LDS directly, one sub-step ahead, and only where the slab's tile has an executable
+      // pair.  MFMA step kk of 32-point half hp takes point 32 hp + 8 (l / 16) + kk of the sub-step, so a
+      // lane reads the 8 values of its row of a slab with two 16-byte loads.
       float *ring = reinterpret_cast<float *>(s_raw);
       const float *Pf = reinterpret_cast<const float *>(phi);
       const float *Zf = reinterpret_cast<const float *>(zws);
       const int m16 = l & 15, g = l >> 4;
-      const int nst = 4 * tot;
-      auto issue = [&](int st) -> int {
-        const int e = st >> 2, sub = st & 3;
+      const int nst = kNS * tot;
+      constexpr int kRowU = kSP / 4;                 // 16-byte units per slab row
+      constexpr int kCopies = kD * kRowU / 64;       // copies of 64 units per wave and slab
+      auto issue = [&](int st) {
+        const int e = st / kNS, sub = st % kNS;
         const int m = __builtin_amdgcn_readfirstlane(s_m[e]);
         const int slab = ws & 3;
         const bool need = ws < 4 ? ((m >> (4 * slab)) & 15) != 0 : ((m >> slab) & 0x1111) != 0;
-        if (!need) return 0;
+        if (!need) return;
         const int info = __builtin_amdgcn_readfirstlane(ws < 4 ? s_ip[e] : s_iq[e]);
         const long long bo = s_bo[e];
-        const float *src = (ws < 4 ? Pf : Zf) + size_t(bo + tile_pos(info, slab)) * (kD * kG) + 32 * sub;
+        const float *src = (ws < 4 ? Pf : Zf) + size_t(bo + tile_pos(info, slab)) * (kD * kG) + kSP * sub;
         float *dst = ring + (st & (kRing - 1)) * kSlotF + ws * kSlab;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+        for (int k = 0; k < kCopies; ++k) {
+          const int tu = 64 * k + l, i = tu / kRowU, cu = (tu % kRowU) ^ (i & 7);
           dma16(src + i * kG + 4 * cu, dst + 256 * k);
         }
-        return 1;
       };
-      // bit k of hist: this wave copied sub-step st + k
-      int hist = 0;
-      for (int j = 0; j < kRing - 1; ++j)
-        if (j < nst) hist |= issue(j) << j;
+      static_assert(kRing == 2, "the waits below assume one sub-step in flight");
+      if (nst > 0) issue(0);
       for (int st = 0; st < nst; ++st) {
-        // this wave's copies of sub-step st have landed (those of st + 1, st + 2 may stay in flight) and
-        // its reads of st - 1 are done; after the barrier the slot of st - 1 takes sub-step st + 3
-        const int ahead = ((hist >> 1) & 1) + ((hist >> 2) & 1);
-        if (ahead == 2) wait_vm_lds<8>(); else if (ahead == 1) wait_vm_lds<4>(); else wait_vm_lds<0>();
+        // this wave's copies of sub-step st have landed and its reads of st - 1 are done; after the
+        // barrier the slot of st - 1 takes sub-step st + 1
+        wait_vm_lds<0>();
         wg_barrier();
-        const int nb = (st + kRing - 1 < nst) ? issue(st + kRing - 1) : 0;
-        hist = (hist >> 1) | (nb << (kRing - 2));
-        const int m = __builtin_amdgcn_readfirstlane(s_m[st >> 2]);
+        if (st + 1 < nst) issue(st + 1);
+        const int m = __builtin_amdgcn_readfirstlane(s_m[st / kNS]);
         const float *sl = ring + (st & (kRing - 1)) * kSlotF;
 #pragma unroll
         for (int P = 0; P < 2; ++P) {
           const int a = pa0 + P, b = P ? pb1 : pb0;
           if (!((m >> (4 * a + b)) & 1) || ((wdiag >> P) & 1)) continue;
-          f4 fa[2][2], fb[2][2];
 #pragma unroll
-          for (int t = 0; t < 2; ++t)
+          for (int hp = 0; hp < kSP / 32; ++hp) {
+            f4 fa[2][2], fb[2][2];
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-              const int off = (16 * t + m16) * kD + 4 * ((2 * g + hh) ^ (m16 & 7));
-              fa[t][hh] = *reinterpret_cast<const f4 *>(sl + a * kSlab + off);
-              fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + off);
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+              for (int hh = 0; hh < 2; ++hh) {
+                const int off = (16 * t + m16) * kSP + 4 * ((8 * hp + 2 * g + hh) ^ (m16 & 7));
+                fa[t][hh] = *reinterpret_cast<const f4 *>(sl + a * kSlab + off);
+                fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + off);
+              }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+              for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+                  acc[P][2 * ti + tj] =
+                      M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3], acc[P][2 * ti + tj]);
+            // FP32 sums of 32 points each, FP64 beyond
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) dacc[P][q][v] += double(acc[P][q][v]);
+              acc[P][q] = acc_t{};
             }
-#pragma unroll
-          for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-            for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-              for (int tj = 0; tj < 2; ++tj)
-                acc[P][2 * ti + tj] = M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3], acc[P][2 * ti + tj]);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dacc[P][q][v] += double(acc[P][q][v]);
-            acc[P][q] = acc_t{};
           }
         }
       }
