@@ -683,7 +683,6 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
                 hipStream_t stream) {
   auto t0 = std::chrono::steady_clock::now();
   check_hip(hipGetDevice(&P.device), "hipGetDevice");
-  check_hip(hipDeviceGetAttribute(&P.n_cu, hipDeviceAttributeMultiprocessorCount, P.device), "device attribute");
   P.opts = *o;
   P.gga = (o->xc != KLDI_XC_LDA_X);
   P.n_mol = n_mol;

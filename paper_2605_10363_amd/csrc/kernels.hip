@@ -201,8 +201,7 @@ struct QArgs {
 };
 
 template <class F>
-__device__ __forceinline__ void run_items(const QArgs &q, int64_t item0, int64_t n_items, F &&run) {
-  (void)n_items;
+__device__ __forceinline__ void run_items(const QArgs &q, int64_t item0, F &&run) {
   const int qx = blockIdx.x & 7;
   const int64_t pos = q.qoff[qx] + (blockIdx.x >> 3);
   if (pos < q.qoff[qx + 1]) run(int64_t(q.order[pos]) - item0);
@@ -252,7 +251,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   __shared__ int s_q[kMaxNp];      // q of each compacted entry (FP32 path)
   __shared__ int s_w[8];
   __shared__ double s_acc[4][4][kG];
-  run_items(A.q, A.item0, A.n_items, [&](int64_t il) {
+  run_items(A.q, A.item0, [&](int64_t il) {
   const int64_t it = A.item0 + il;
   const int64_t r = A.xit_r[it];
   const int c = A.xit_c[it];
@@ -380,7 +379,8 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
     // the FP32 accumulators of sub-tile row ti are added to the FP64 sums every 8 MFMA steps (one K
     // tile), row 0 after step 3 and row 1 after step 7 of each K tile, so the conversion and FP64 adds
     // of one row overlap the MFMAs of the other.  (Measured at the 200-atom chain: flushing after every
-    // second K tile saves 4% of this kernel but raises the E_xc error sevenfold.)
+    // second K tile saves 4% of this kernel but raises the E_xc error sevenfold; flushing the two waves of
+    // a SIMD at different steps changes nothing.)
     auto flush = [&](int ti) {
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) {
@@ -728,7 +728,7 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   __shared__ int s_ip[NTV], s_iq[NTV];
   __shared__ long long s_bo[NTV];
   __shared__ int s_w[8];
-  run_items(A.q, A.item0, A.n_items, [&](int64_t il) {
+  run_items(A.q, A.item0, [&](int64_t il) {
   const int64_t item = A.item0 + il;
   const VItem it = A.items[item];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;

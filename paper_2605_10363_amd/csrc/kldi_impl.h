@@ -132,7 +132,6 @@ struct Queues {
 
 struct Plan {
   int device = 0;
-  int n_cu = 0;
   kldi_opts opts{};
   bool gga = false;
   int n_mol = 0;
