@@ -167,3 +167,57 @@ def test_grid_chunks_give_identical_results(Plan, cfg0, xc):
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
     assert (sa["n_pairs_x"], sa["n_pairs_v"]) == (sb["n_pairs_x"], sb["n_pairs_v"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_density_matrix_gives_exact_zeros(Plan, prec):
+    """D = 0: every a_pq is 0, so no (p, q) pair is executable (eq. block_pair_filter); rho = 0 gives
+    f = v = 0 below the density floor, so Z, every Vxc pair and Vxc vanish.  The oracle gives the same
+    exact zeros; the retained structure (which depends on the basis and grid only) is unchanged."""
+    p = synth.tiny_problem(n_atoms=3, n_rad=12, n_ang=26, n_occ=3, xc="pbe", seed=47)
+    Dz = np.zeros_like(p.D)
+    ref = oracle.eval_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, Dz, "pbe",
+                              t_b=1e-10, t_d=1e-10, d_ao=32, G=128)
+    assert ref["E"] == 0.0 and (ref["nP_X"], ref["nP_M"]) == (0, 0)
+    print("case: zero D, pbe, prec=%s" % prec, flush=True)
+    plan = Plan.from_problem(p, xc="pbe", prec=prec)
+    assert plan.info()["n_retained_tiles"] > 0
+    rho, exc, vxc = plan.eval(torch.zeros(p.n_ao, p.n_ao, dtype=torch.float64, device="cuda"))
+    st = plan.check()
+    assert float(exc.item()) == 0.0
+    assert not torch.any(rho != 0).item() and not torch.any(vxc != 0).item()
+    assert (st["n_pairs_x"], st["n_pairs_v"]) == (0, 0)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_thresholds_that_retain_nothing(Plan, prec):
+    """t_b = t_d = 1e300: no (tile, block) pair is retained (eq. retained_blocks_B), so the plan has no X or
+    Vxc work items; every output is an exact zero, as in the oracle at the same thresholds."""
+    p = synth.tiny_problem(n_atoms=3, n_rad=12, n_ang=26, n_occ=3, xc="pbe", seed=47)
+    ref = blocked_ref(p, "pbe", t_b=1e300, t_d=1e300)
+    assert ref["E"] == 0.0 and ref["S_phi"].sum() == 0
+    g = run(Plan, p, "pbe", prec=prec, t_b=1e300, t_d=1e300)
+    assert g["info"]["n_retained_tiles"] == 0 and g["info"]["n_v_items"] == 0
+    assert g["E"] == 0.0 and not np.any(g["rho"]) and not np.any(g["V"])
+    assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (0, 0)
+    g["plan"].close()
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_grid_smaller_than_one_block(Plan, xc):
+    """One atom, 15 AOs (a tile with 17 padding rows) and 78 points (one block with 50 padding points of
+    weight 0): FP64 to the blocked oracle at 1e-12, the mixed form within its targets."""
+    p = synth.tiny_problem(n_atoms=1, n_rad=3, n_ang=26, n_occ=1, xc=xc, seed=48, box_A=3.0)
+    assert p.n_ao < 32 and p.n_points < 128
+    ref = blocked_ref(p, xc)
+    g = run(Plan, p, xc, prec="fp64")
+    assert abs(g["E"] - ref["E"]) <= 1e-12 * abs(ref["E"])
+    assert np.abs(g["V"] - ref["V"]).max() <= 1e-12 * np.abs(ref["V"]).max()
+    assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * np.abs(ref["rho"]).max()
+    assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
+    g["plan"].close()
+    f = run(Plan, p, xc, prec="fp32")
+    assert abs(f["E"] - ref["E"]) < 1e-6 and np.abs(f["V"] - ref["V"]).max() < 1e-7
+    assert np.array_equal(f["V"], f["V"].T)
+    f["plan"].close()
