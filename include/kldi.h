@@ -168,8 +168,10 @@ void kldi_opts_default(kldi_opts *opts);
  * lists BCS(C) (Appendix C), the Vxc work list, and all device workspaces.
  * basis, grid, opts: host pointers (copied).  stream: hipStream_t or NULL.  *out receives the
  * plan, owned by the caller and released with kldi_plan_destroy.
- * Errors: KLDI_E_ARG (validation), KLDI_E_UNSUPPORTED (grid_block != 128, ao_block != 32),
- * KLDI_E_OOM, KLDI_E_HIP.  On error *out is set to NULL and nothing is leaked. */
+ * Errors: KLDI_E_ARG (validation), KLDI_E_UNSUPPORTED (grid_block != 128, ao_block != 32, or more
+ * than 512 retained AO tiles, i.e. 16,384 AOs, in one grid block), KLDI_E_OOM, KLDI_E_HIP.  On error
+ * *out is set to NULL and nothing is leaked.  A plan with no retained tile (thresholds above every block
+ * maximum) is valid: its evaluations return exact zeros. */
 kldi_status kldi_plan_create(const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts,
                              void *stream, kldi_plan **out);
 
