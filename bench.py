@@ -7,7 +7,7 @@ with the density epilogue, the functional, Z, the M = Phi Z^T block GEMMs, the F
 the symmetrised Vxc.  The mixed path (FP32 MFMA, FP64 accumulation) is the headline; the FP64
 path is timed beside it on the same inputs.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: libkldi runs on one GPU.
 """
 import argparse
 import hashlib
@@ -317,7 +317,7 @@ def main():
                     help="also run one plain 1 GiB device copy (HBM-counter calibration for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus)
+        print("bench.py runs on one GPU only (libkldi has no multi-GPU path); got --gpus %d" % args.gpus)
         sys.exit(2)
 
     import torch

@@ -49,7 +49,7 @@ typedef enum {
   KLDI_E_ARG = -1,          /* invalid argument (NULL pointer, bad size, bad enum, ...)          */
   KLDI_E_OOM = -2,          /* device memory for the plan's workspaces could not be allocated    */
   KLDI_E_HIP = -3,          /* a HIP runtime call failed                                          */
-  KLDI_E_UNSUPPORTED = -4,  /* valid request this build does not implement                       */
+  KLDI_E_UNSUPPORTED = -4,  /* valid request this library does not implement                     */
   KLDI_E_STATE = -5,        /* call out of order                                                  */
   KLDI_E_NONFINITE = -6     /* non-finite entry found in D (reported by kldi_eval_check)          */
 } kldi_status;
@@ -107,8 +107,8 @@ typedef struct {
   double t_b;                    /* block-retention threshold (eq. block_filter_A), >= 0          */
   double t_d;                    /* block-pair execution threshold (eq. block_pair_filter), >= 0  */
   double rho_cut;                /* points with rho <= rho_cut get f = v = 0, >= 0                 */
-  int32_t grid_block;            /* G, points per grid block; this build supports 128             */
-  int32_t ao_block;              /* d, AOs per tile; this build supports 32                       */
+  int32_t grid_block;            /* G, points per grid block; the library supports 128             */
+  int32_t ao_block;              /* d, AOs per tile; the library supports 32                       */
   int32_t prec;                  /* kldi_prec                                                     */
   int32_t xc;                    /* kldi_xc                                                       */
   int32_t v_segment;             /* grid blocks per Vxc work item (the K extent of its tile);

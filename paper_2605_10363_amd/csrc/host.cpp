@@ -167,8 +167,8 @@ void validate_opts(const kldi_opts *o) {
       !std::isfinite(o->t_d) || !std::isfinite(o->rho_cut))
     fail(KLDI_E_ARG, "t_b, t_d and rho_cut must be finite and >= 0");
   if (o->grid_block <= 0 || o->grid_block % 64 != 0) fail(KLDI_E_ARG, "grid_block must be a positive multiple of 64");
-  if (o->grid_block != kG) fail(KLDI_E_UNSUPPORTED, "this build supports grid_block = 128");
-  if (o->ao_block != kD) fail(KLDI_E_UNSUPPORTED, "this build supports ao_block = 32");
+  if (o->grid_block != kG) fail(KLDI_E_UNSUPPORTED, "libkldi supports grid_block = 128");
+  if (o->ao_block != kD) fail(KLDI_E_UNSUPPORTED, "libkldi supports ao_block = 32");
   if (o->prec != KLDI_PREC_FP64 && o->prec != KLDI_PREC_FP32) fail(KLDI_E_ARG, "unknown prec");
   if (o->xc != KLDI_XC_LDA_X && o->xc != KLDI_XC_PBE && o->xc != KLDI_XC_PBE_X) fail(KLDI_E_ARG, "unknown xc");
   if (o->v_segment < 0) fail(KLDI_E_ARG, "v_segment must be >= 0");
