@@ -31,7 +31,9 @@
  *  - All public floating-point data is FP64 whatever the internal precision.  Matrices are dense,
  *    row-major, n_ao x n_ao, in the caller's AO order; rho is in the caller's grid order.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  kldi_eval only enqueues
- *    work; results are ready after the stream is synchronised.
+ *    work; results are ready after the stream is synchronised.  Part of an FP32 evaluation runs on a
+ *    stream of the plan forked from `stream` and joined back into it, so ordering on `stream` holds;
+ *    evaluations of one plan on different streams at the same time are not supported.
  *  - Arguments are validated before any launch.  A plan is not re-entrant: concurrent kldi_eval
  *    calls on one plan race on its workspaces.
  */

@@ -79,6 +79,11 @@ void free_plan(Plan &P) {
   free_graphs(P);
   if (P.cap_stream) (void)hipStreamDestroy(P.cap_stream);
   P.cap_stream = nullptr;
+  if (P.side_stream) (void)hipStreamDestroy(P.side_stream);
+  P.side_stream = nullptr;
+  if (P.fork_ev) (void)hipEventDestroy(P.fork_ev);
+  if (P.join_ev) (void)hipEventDestroy(P.join_ev);
+  P.fork_ev = P.join_ev = nullptr;
   free_list(P.sched_allocs);
   free_list(P.allocs);
   for (hipEvent_t e : P.events) (void)hipEventDestroy(e);
@@ -925,6 +930,9 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
   check_hip(hipStreamSynchronize(stream), "plan sync");
 
   build_schedule(P, o->v_segment, o->schedule, o->chunk_tiles);
+  check_hip(hipStreamCreateWithFlags(&P.side_stream, hipStreamNonBlocking), "hipStreamCreate");
+  check_hip(hipEventCreateWithFlags(&P.fork_ev, hipEventDisableTiming), "hipEventCreate");
+  check_hip(hipEventCreateWithFlags(&P.join_ev, hipEventDisableTiming), "hipEventCreate");
   P.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

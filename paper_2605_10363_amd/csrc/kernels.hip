@@ -966,8 +966,9 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
 // FP32 plans: the diagonal tiles M_pp of the Vxc product in FP64.  One workgroup per Vxc item of a
 // diagonal chunk pair (pc = qc); wave w owns the tile p = 4 pc + w and walks the segment's blocks whose
 // pair mask executes (p, p) (eq. block_pair_filter, as k_vgemm), M_pp += Phi_pr Z_pr^T on FP64 MFMA with
-// the operand Phi_hi + Phi_lo; the result goes to the tile's place in the item's partial, which
-// k_vgemm wrote for every other tile.
+// the operand Phi_hi + Phi_lo; the result goes to the tile's place in the item's partial, whose other
+// tiles k_vgemm writes.  The two kernels share no output, so they run concurrently (an item in which
+// nothing executes gets zeros here and is skipped by the reduction).
 struct VDArgs {
   StructDev st;
   const VItem *items;
@@ -981,13 +982,11 @@ struct VDArgs {
   const float *phi;
   const unsigned short *phil;
   const float *zws;
-  const int *vflag;
   double *vpart;
 };
 
 __global__ __launch_bounds__(NT) void k_vdiag(VDArgs A) {
   const int64_t item = A.ditems[blockIdx.x];
-  if (!A.vflag[item]) return;     // nothing executed in this item: k_vgemm wrote no partial
   const VItem it = A.items[item];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   d4 dd[2][2];
@@ -1220,9 +1219,17 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
       va.counters = E.counters;
       va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci};
       const int64_t gv = 8 * P.vq.maxlen_h[ci];
-      if (nvit > 0) k_vgemm<T><<<gv, NTV, 0, s>>>(va);
       const int64_t nd = P.dchunk_h[ci + 1] - P.dchunk_h[ci];
-      if (sizeof(T) == 4 && nd > 0) {
+      const bool diag = sizeof(T) == 4 && nd > 0;
+      // k_vdiag needs what k_vmask and the stages before it wrote and shares no output with k_vgemm: it
+      // runs on the side stream beside k_vgemm, which joins back before the next use of the workspaces
+      if (diag) {
+        hipError_t e = hipEventRecord(P.fork_ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.side_stream, P.fork_ev, 0);
+        if (e != hipSuccess) return e;
+      }
+      if (nvit > 0) k_vgemm<T><<<gv, NTV, 0, s>>>(va);
+      if (diag) {
         VDArgs da;
         da.st = P.st;
         da.items = P.items;
@@ -1237,9 +1244,11 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
         da.phi = static_cast<const float *>(E.phi);
         da.phil = E.phil;
         da.zws = static_cast<const float *>(E.zws);
-        da.vflag = E.vflag;
         da.vpart = E.vpart;
-        k_vdiag<<<nd, NT, 0, s>>>(da);
+        k_vdiag<<<nd, NT, 0, P.side_stream>>>(da);
+        hipError_t e = hipEventRecord(P.join_ev, P.side_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, P.join_ev, 0);
+        if (e != hipSuccess) return e;
       }
     }
   }
