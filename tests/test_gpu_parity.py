@@ -149,15 +149,17 @@ def test_rho_only_and_no_vxc(Plan):
     plan.close()
 
 
-@pytest.mark.parametrize("xc", ["lda", "pbe"])
-def test_grid_chunks_give_identical_results(Plan, cfg0, xc):
+@pytest.mark.parametrize("xc,prec", [("lda", "fp64"), ("pbe", "fp64"), ("lda", "fp32"), ("pbe", "fp32")])
+def test_grid_chunks_give_identical_results(Plan, cfg0, xc, prec):
     """Processing the grid in several chunks of whole Vxc segments (small Phi/Z workspaces) must give
-    bit-identical results to one chunk: the same work items run, and every sum keeps its order."""
+    bit-identical results to one chunk: the same work items run, and every sum keeps its order.  With FP32
+    operands the diagonal Vxc tiles of each chunk run on the side stream and must be joined before the
+    next chunk overwrites the workspaces."""
     p = cfg0
     D = torch.from_numpy(p.D).cuda()
     outs = []
     for ct in (0, 40):
-        plan = Plan.from_problem(p, xc=xc, v_segment=16, chunk_tiles=ct)
+        plan = Plan.from_problem(p, xc=xc, prec=prec, v_segment=16, chunk_tiles=ct)
         info = plan.info()
         print("chunk_tiles=%d -> %d grid chunks" % (ct, info["n_grid_chunks"]), flush=True)
         outs.append(([t.cpu().numpy().copy() for t in plan.eval(D)], plan.check(), info["n_grid_chunks"]))
