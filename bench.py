@@ -266,7 +266,7 @@ def bench_learned(args, torch):
         if tag == "mlp":
             plan.attach_mlp(net)
         ms, stage, st, E, V, rho = time_path(plan, D4, args.steps, args.warmup, torch)
-        out_runs[tag] = dict(ms=ms, stage=stage, st=st, E=E, V=V)
+        out_runs[tag] = dict(ms=ms, stage=stage, st=st, E=E, V=V, chunks=plan.info()["n_grid_chunks"])
         log("%s: %.3f ms/eval, functional stage %.3f ms, E %.10f, surrogate points %d" % (
             tag, ms, stage["xfunc"], E, st["n_points_mlp"]))
         plan.close()
@@ -300,6 +300,18 @@ def bench_learned(args, torch):
                                                "sample": "200000 training-range points"},
         },
     }
+    # roofline of the dominant block-GEMM kernel of the run with the network (as for the single-molecule
+    # line; with several grid chunks the combined stage and the GEMM work of the whole evaluation)
+    if m["chunks"] > 1:
+        kernel = "k_xgemm + k_vgemm (%d grid chunks: combined stage)" % m["chunks"]
+        achieved = m["st"]["gemm_flops"] / (m["stage"]["vgemm"] * 1e-3) / 1e12
+    else:
+        dom = "xgemm" if m["stage"]["xgemm"] >= m["stage"]["vgemm"] else "vgemm"
+        kernel = "k_" + dom
+        pairs = m["st"]["n_pairs_x"] if dom == "xgemm" else m["st"]["n_pairs_v"]
+        achieved = 2.0 * 32 * 32 * 128 * pairs / (m["stage"][dom] * 1e-3) / 1e12
+    out["roofline"] = {"bound": "mfma", "kernel": kernel, "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32"],
+                       "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": None}
     print(json.dumps(out), flush=True)
 
 
