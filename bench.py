@@ -22,6 +22,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+DTYPE = {"fp32": "f32", "bf16x6": "bf16x6 (split)", "bf16x3": "bf16x3 (split)", "fp64": "f64"}
+PATHS = {"fp32": "mixed: FP32 MFMA block GEMMs, FP64 functional and accumulation",
+         "bf16x6": "mixed: X = D Phi as six BF16-MFMA products of three-piece splits, Vxc on FP32 MFMA, "
+                   "FP64 functional and accumulation",
+         "bf16x3": "mixed: X = D Phi as three BF16-MFMA products of two-piece splits, Vxc on FP32 MFMA, "
+                   "FP64 functional and accumulation",
+         "fp64": "FP64 MFMA block GEMMs"}
 METRIC = "ms per EXC eval (rho+E_xc+Vxc) & TFLOP/s, mixed vs FP64, at 1e-6 Eh error"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X dense MFMA peaks
 GOLDEN = os.path.join(ROOT, "tests", "golden", "cfg1_oracle.json")            # dense (unscreened)
@@ -327,6 +334,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=10, help="training epochs of the learned form (--config 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--ao-order", default="both", choices=["atom", "both"],
+                    help="both: also time the headline form with the overlap-signature basis order (workload 1)")
+    ap.add_argument("--precs", default="fp32,bf16x6,bf16x3",
+                    help="precision forms timed beside FP64 (workloads 1 and 2); the first is the headline value")
     ap.add_argument("--v-segment", type=int, default=0, help="grid blocks per Vxc segment (0 = plan's choice)")
     ap.add_argument("--schedule", default="grid", choices=["grid", "queue", "auto"],
                     help="work-item schedule of the GEMM kernels (auto: the plan's autotuner picks it and the "
@@ -361,7 +372,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
     res = {}
-    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
+    forms = [f for f in args.precs.split(",") if f]
+    for prec in (forms if args.no_fp64 else forms + ["fp64"]):
         t0 = time.time()
         plan = Plan.from_problem(p, prec=prec, v_segment=args.v_segment,
                                  schedule="grid" if args.schedule == "auto" else args.schedule)
@@ -381,14 +393,14 @@ def main():
         del rho
         torch.cuda.empty_cache()
 
-    mix = res["fp32"]
+    mix = res[forms[0]]
     flops = mix["stats"]["gemm_flops"]
     out = {
         "metric": METRIC, "value": round(mix["ms"], 4), "unit": "ms/eval", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(mix["ms"], 4), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": DTYPE[forms[0]], "data": "synthetic",
         "config": {"workload": WORKLOADS.get(args.config, "config %d" % args.config),
-                   "path": "mixed: FP32 MFMA block GEMMs, FP64 functional and accumulation",
+                   "path": PATHS[forms[0]],
                    "seeds": p.meta.get("seeds")},
         "tflops": round(flops / (mix["ms"] * 1e-3) / 1e12, 3),
         "gemm_flops_per_eval": flops,
@@ -402,6 +414,15 @@ def main():
                        "stage_ms": {k: round(v, 4) for k, v in f64["stage"].items()}}
         out["speedup_mixed_vs_fp64"] = round(f64["ms"] / mix["ms"], 3)
         out["err_mixed_vs_fp64"] = {"E_xc": abs(mix["E"] - f64["E"]), "V_maxabs": float(np.abs(mix["V"] - f64["V"]).max())}
+    out["precision_forms"] = {}
+    for prec in forms:
+        r = res[prec]
+        d = {"ms": round(r["ms"], 4), "tflops": round(r["stats"]["gemm_flops"] / (r["ms"] * 1e-3) / 1e12, 3),
+             "stage_ms": {k: round(v, 4) for k, v in r["stage"].items()}, "path": PATHS[prec]}
+        if "fp64" in res:
+            d["err_vs_fp64"] = {"E_xc": abs(r["E"] - res["fp64"]["E"]),
+                                "V_maxabs": float(np.abs(r["V"] - res["fp64"]["V"]).max())}
+        out["precision_forms"][prec] = d
     if args.config == 1:
         out["err_vs_oracle"] = {}
         for tag, path in (("blocked", GOLDEN_BLOCKED), ("dense", GOLDEN)):
@@ -414,6 +435,31 @@ def main():
                 dv = max(np.abs(V[ij[:, 0], ij[:, 1]] - np.array(g["v"])).max(),
                          np.abs(np.diag(V) - np.array(g["v_diag"])).max())
                 out["err_vs_oracle"]["%s_%s" % (tag, prec)] = {"E_xc": abs(r["E"] - g["E"]), "V_maxabs_sampled": dv}
+
+    if args.config == 1 and args.ao_order == "both":
+        from paper_2605_10363_amd.plan import overlap_order
+        S = synth.overlap_matrix(p.basis, p.atom_xyz)   # an input (the SCF setup has it), not timed
+        t0 = time.time()
+        _, so = overlap_order(p.basis, S)
+        order_ms = (time.time() - t0) * 1e3
+        plan = Plan.from_problem(p, prec=forms[0], v_segment=args.v_segment, shell_order=so)
+        info = plan.info()
+        ms, stage, st, E, V, rho = time_path(plan, D, args.steps, args.warmup, torch)
+        log("%s, overlap-clustered basis order: %.3f ms/eval, retained fraction %.4f, pairs x %d v %d (order %.0f ms)" % (
+            forms[0], ms, info["retained_fraction"], st["n_pairs_x"], st["n_pairs_v"], order_ms))
+        out["ao_order_overlap"] = {
+            "what": "the headline form with basis functions ordered by overlap-signature clustering (kldi_overlap_order) "
+                    "instead of atom order",
+            "order_ms": round(order_ms, 1), "ms": round(ms, 4), "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+            "retained_fraction": info["retained_fraction"], "n_retained_tiles": info["n_retained_tiles"],
+            "n_pairs_x": st["n_pairs_x"], "n_pairs_v": st["n_pairs_v"],
+            "atom_order": {"ms": round(mix["ms"], 4), "retained_fraction": mix["info"]["retained_fraction"],
+                           "n_retained_tiles": mix["info"]["n_retained_tiles"],
+                           "n_pairs_x": mix["stats"]["n_pairs_x"], "n_pairs_v": mix["stats"]["n_pairs_v"]},
+            "E_xc_diff_vs_atom_order": abs(E - mix["E"])}
+        plan.close()
+        del rho
+        torch.cuda.empty_cache()
 
     # roofline of the dominant kernel (the larger of the two block-GEMM stages), timed live above.  A plan
     # that processes the grid in several chunks interleaves the stages, so only the GEMM work of the whole

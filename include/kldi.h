@@ -68,7 +68,14 @@ typedef enum {
  * the Vxc accumulation across grid segments are FP64 in every mode. */
 typedef enum {
   KLDI_PREC_FP64 = 0,       /* FP64 operands, FP64 MFMA (v_mfma_f64_16x16x4)                     */
-  KLDI_PREC_FP32 = 1        /* FP32 operands, FP32 MFMA accumulate, FP64 flush                    */
+  KLDI_PREC_FP32 = 1,       /* FP32 operands, FP32 MFMA accumulate, FP64 flush                    */
+  /* Split-precision products on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation within one
+   * 32-AO K tile, FP64 flush) for the X = D Phi product: each FP64 operand is written as a sum of
+   * BF16 pieces v = v_0 + v_1 (+ v_2), each piece the BF16 rounding of what the earlier ones leave,
+   * and the products of pieces whose orders add up to at most 1 (X3) or 2 (X6) are summed.  The
+   * Vxc product runs as in KLDI_PREC_FP32. */
+  KLDI_PREC_BF16X3 = 3,     /* two pieces, 3 products: about 16 significant bits per product      */
+  KLDI_PREC_BF16X6 = 4      /* three pieces, 6 products: about 24 significant bits per product    */
 } kldi_prec;
 
 /* Contracted cartesian Gaussian basis (Appendix A, "Gaussian basis functions"):
@@ -102,7 +109,9 @@ typedef enum {
   KLDI_SCHED_GRID = 0,      /* grid blocks (X) / Vxc segments dealt round-robin over the 8 XCDs,
                                Vxc items in decreasing estimated cost; one workgroup per item      */
   KLDI_SCHED_QUEUE = 1      /* 8 per-XCD queues of about equal estimated cost (items of a queue
-                               share L2), each ordered by decreasing cost; one workgroup per item */
+                               share L2), each ordered by decreasing cost; one workgroup per item.
+                               Plans of more than 1024 grid blocks refuse it (KLDI_E_UNSUPPORTED):
+                               it has been verified only on smaller plans                          */
 } kldi_schedule;
 
 typedef struct {
@@ -118,6 +127,10 @@ typedef struct {
   int32_t chunk_tiles;           /* max retained tiles whose Phi/Z are held at once (the grid is
                                     processed in chunks of whole Vxc segments); 0 = fit to memory */
   int32_t schedule;              /* kldi_schedule                                                 */
+  const int32_t *shell_order;    /* NULL: basis functions in the atom order (atoms by the Morton key
+                                    of their centres, each atom's shells in input order); else host
+                                    array [n_shells], the internal sequence of (caller) shells, e.g.
+                                    from kldi_overlap_order; read at plan time; single-molecule plans */
 } kldi_opts;
 
 typedef struct kldi_plan kldi_plan;
@@ -207,7 +220,7 @@ typedef struct {
 
 /* Autotuner: times evaluations of this plan with D_dev (device, packed as for kldi_eval) for each
  * candidate Vxc tile depth (v_segment in {8, 16, 32, 64} whose FP64 partials fit in memory) and each
- * kldi_schedule, reps timed evaluations each after one warm-up, keeps the fastest, and records it in
+ * kldi_schedule the plan's size admits (KLDI_SCHED_QUEUE up to 1024 grid blocks), reps timed evaluations each after one warm-up, keeps the fastest, and records it in
  * an in-process cache keyed by the plan's shape (molecules, AOs, blocks, retained tiles, functional,
  * precision) that later plans of the same shape reuse without timing.  Synchronises `stream`.
  * Writes the choice to *out (host, may be NULL).  reps >= 1; reps = 0 only consults the cache. */
@@ -294,7 +307,8 @@ kldi_status kldi_mlp_train(kldi_mlp *mlp, const double *rho_dev, const double *s
 
 /* f, v_rho, v_sigma at n points (FP64 device arrays) from the network where it covers the point
  * (rho >= rho_min, features inside the box), else from the analytic functional it was trained on.
- * used_dev[n] (device, may be NULL) receives 1 where the network was used. */
+ * used_dev[n] (device, may be NULL) receives 1 where the network was used.  KLDI_E_STATE before the
+ * network has been trained (it has no range box or target statistics yet). */
 kldi_status kldi_mlp_forward(const kldi_mlp *mlp, const double *rho_dev, const double *sigma_dev, int64_t n,
                              double *f_dev, double *vrho_dev, double *vsigma_dev, int32_t *used_dev, void *stream);
 
@@ -304,13 +318,45 @@ kldi_status kldi_mlp_forward(const kldi_mlp *mlp, const double *rho_dev, const d
 kldi_status kldi_mlp_loss_grad(kldi_mlp *mlp, const float *x_dev, const float *t_dev, int64_t n, double *loss_host,
                                float *grad_host, void *stream);
 
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step size lr > 0) on one batch, for checks of
+ * the update: the gradient of the batch exactly as kldi_mlp_loss_grad returns it, then the moment
+ * and parameter update of the training kernels (FP32 master weights; the BF16 copy is refreshed).
+ * x_dev, t_dev as for kldi_mlp_loss_grad; *loss_host (host, may be NULL) = the batch loss before the
+ * step.  Advances the network's step count, which sets the bias corrections 1 - beta^k.
+ * Synchronises `stream`. */
+kldi_status kldi_mlp_step(kldi_mlp *mlp, const float *x_dev, const float *t_dev, int64_t n, double lr,
+                          double *loss_host, void *stream);
+
+/* Basis-function order by overlap-signature clustering (Sec. III-B.2, "Locality-Preserving
+ * Reordering"; appendix on reordering details, eqs. overlap_signature, cosine_similarity,
+ * cosine_distance).  Row i of the overlap matrix is the signature of basis function i; functions are
+ * compared by the cosine distance of their signatures; average-linkage agglomerative clustering
+ * merges clusters until one remains, each merge joining the leaf sequences of its two sub-trees (the
+ * earlier-formed first) with each sub-tree taken forward or reversed so that the two leaves that
+ * meet are the closest of the four possible junctions.  The leaf order of the tree is the basis
+ * permutation.
+ *   S_host          [n_ao * n_ao] host, the symmetric overlap matrix in caller AO order (row-major;
+ *                   n_ao follows from basis->shell_l), finite with no zero row
+ *   ao_order_out    [n_ao] host or NULL: the leaf order (caller AO indices)
+ *   shell_order_out [n_shells] host: the order the library applies (a shell's components stay
+ *                   together): shells sorted stably by the first leaf position of any component;
+ *                   pass it as kldi_opts.shell_order
+ * Host work only, O(n_ao^2) memory and O(n_ao^3 / threads) time for the signature products.
+ * Errors: KLDI_E_ARG, KLDI_E_OOM. */
+kldi_status kldi_overlap_order(const kldi_basis *basis, const double *S_host, int32_t *ao_order_out,
+                               int32_t *shell_order_out);
+
 /* Host copies of the parameters (FP32 master, [8707]) and of the training statistics (box[4],
  * tmean[3], tstd[3]); any pointer may be NULL.  set_params (host) overwrites the parameters. */
 kldi_status kldi_mlp_params(kldi_mlp *mlp, float *get_params, const float *set_params, double *box, double *tmean,
                             double *tstd);
 
 /* Evaluations of a GGA plan then use the trained network in place of the analytic functional where
- * it covers a point (NULL detaches).  The plan keeps a view: the network must outlive the plan's use. */
+ * it covers a point (NULL detaches).  The plan keeps a view of the network's device memory (weights,
+ * range box, target statistics), so training the network again after attaching is seen by the next
+ * evaluation and by replays of a captured graph; the network must outlive the plan's use of it.
+ * Errors: KLDI_E_UNSUPPORTED (LDA plan), KLDI_E_STATE (network not trained), KLDI_E_ARG (network
+ * trained on another functional than the plan's). */
 kldi_status kldi_plan_attach_mlp(kldi_plan *plan, const kldi_mlp *mlp);
 
 /* Turns per-stage timing on (enable != 0) or off and clears the accumulated samples.  While on,
@@ -326,7 +372,7 @@ kldi_status kldi_eval_timing(kldi_plan *plan, double *stage_ms, int32_t *n_evals
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *kldi_last_error(void);
 
-/* ABI version, currently 2. */
+/* ABI version, currently 3. */
 int32_t kldi_version(void);
 
 #ifdef __cplusplus

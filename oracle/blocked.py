@@ -39,12 +39,12 @@ from . import reorder as _reorder
 
 
 def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_d=1e-10,
-                 d_ao=32, G=128, rho_cut=1e-14):
+                 d_ao=32, G=128, rho_cut=1e-14, shell_order=None):
     atom_xyz = np.asarray(atom_xyz, np.float64)
     pts = np.asarray(pts, np.float64)
     w = np.asarray(weights, np.float64)
     gga = _fx.is_gga(xc)
-    ao_perm, pt_perm, _ = _reorder.orders(atom_xyz, basis, pts, point_atom)
+    ao_perm, pt_perm, _ = _reorder.orders(atom_xyz, basis, pts, point_atom, shell_order)
     nao = len(ao_perm)
     npt = len(pt_perm)
     phi_c, dphi_c = _basis.eval_ao(atom_xyz, basis, pts, deriv=1)
@@ -147,7 +147,7 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
 
 
 def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_d=1e-10, d_ao=32, G=128,
-                        rho_cut=1e-14, blocks_per_chunk=32, v_entries=None, progress=None):
+                        rho_cut=1e-14, blocks_per_chunk=32, v_entries=None, progress=None, shell_order=None):
     """The same block-filtered evaluation as eval_blocked, one grid block at a time, for inputs whose
     dense Phi does not fit in memory.
 
@@ -166,7 +166,7 @@ def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e
     pts = np.asarray(pts, np.float64)
     w = np.asarray(weights, np.float64)
     gga = _fx.is_gga(xc)
-    ao_perm, pt_perm, _ = _reorder.orders(atom_xyz, basis, pts, point_atom)
+    ao_perm, pt_perm, _ = _reorder.orders(atom_xyz, basis, pts, point_atom, shell_order)
     nao = len(ao_perm)
     npt = len(pt_perm)
     Dp = np.asarray(D, np.float64)[np.ix_(ao_perm, ao_perm)]

@@ -130,3 +130,50 @@ def from_targets(rho, t):
     r13 = np.cbrt(rho)
     r43 = rho * r13
     return t[:, 0] * r43, t[:, 1] * r13, t[:, 2] / r43
+
+
+# --------------------------------------------------------------------------------------------
+# BF16 inference: the network with BF16 weights, and a bound on what the rest of the rounding adds
+# --------------------------------------------------------------------------------------------
+BF16_UNIT = 2.0 ** -8        # unit roundoff of bfloat16 (8 significant bits), round to nearest even
+FP32_UNIT = 2.0 ** -24
+
+
+def bf16_round(a):
+    """Round to the nearest bfloat16 (ties to even), via FP32; returned as float64."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _gamma(n):
+    return n * FP32_UNIT / (1.0 - n * FP32_UNIT)
+
+
+def bf16_inference(theta, x):
+    """Standardised heads of the network whose weight matrices are rounded to BF16 (biases kept as
+    given), evaluated in FP64, and a first-order bound per point and head on how far an evaluation
+    that also (i) rounds the features to FP32, (ii) accumulates every layer's products in FP32,
+    (iii) evaluates SiLU in FP32 and (iv) rounds every hidden activation to BF16 can lie from it.
+
+    The bound is a running error bound carried forward through the layers: an error e in a layer's
+    inputs reaches its pre-activations as |W| e; FP32 accumulation of n products adds at most
+    gamma_n (|W| |h| + |b|), gamma_n = n u / (1 - n u); SiLU passes an error through with |SiLU'|
+    and adds its own evaluation error, bounded by (8 + 2|a|) u |SiLU(a)|; rounding to BF16 adds
+    BF16_UNIT |h|.  Second-order terms are neglected (each is below 1e-3 of the first-order ones).
+    """
+    p = unpack(theta)
+    W = {k: bf16_round(p[k]) for k in ("W1", "W2", "W3", "W4")}
+    x = np.asarray(x, np.float64)
+    e = FP32_UNIT * np.abs(x)                       # features rounded to FP32
+    h = x
+    for k, b in (("W1", "b1"), ("W2", "b2"), ("W3", "b3")):
+        a = h @ W[k].T + p[b]
+        n = W[k].shape[1] + 1
+        ea = e @ np.abs(W[k]).T + _gamma(n) * (np.abs(h) @ np.abs(W[k]).T + np.abs(p[b]))
+        hn = silu(a)
+        e = np.abs(dsilu(a)) * ea + (8.0 + 2.0 * np.abs(a)) * FP32_UNIT * np.abs(hn) + BF16_UNIT * np.abs(hn)
+        h = hn
+    y = h @ W["W4"].T + p["b4"]
+    ey = e @ np.abs(W["W4"]).T + _gamma(W["W4"].shape[1] + 1) * (np.abs(h) @ np.abs(W["W4"]).T + np.abs(p["b4"]))
+    return y, ey + FP32_UNIT * np.abs(y)

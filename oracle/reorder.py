@@ -10,9 +10,9 @@ Readings where the paper is silent:
   before scaling, and the scaled integers are clamped to [0, 2^20 - 1];
 * the "associated atom" of a point is the atom whose atom-centred grid generated it;
 * the groups follow one atom order, the atoms sorted (stably) by the Morton key of their centres;
-* basis functions: the paper's overlap-signature clustering is not used; AOs are ordered by the
-  same atom order, each atom's shells kept in their input order and each shell's components
-  contiguous.
+* basis functions, by default: AOs ordered by the same atom order, each atom's shells kept in their
+  input order and each shell's components contiguous; or, given a shell order (the paper's overlap-
+  signature clustering, oracle.cluster), the shells in that order, components contiguous.
 
 Also here: the cut into AO tiles of d_ao consecutive (internal) AOs and grid blocks of G
 consecutive (internal) points, the last of each ragged (Sec. III-B.1: M_r = ceil(M/d) etc.).
@@ -55,8 +55,9 @@ def atom_order(atom_xyz, origin):
     return np.argsort(key, kind="stable")
 
 
-def orders(atom_xyz, basis, pts, point_atom):
-    """Returns (ao_perm, pt_perm, atom_perm): internal index -> caller index for AOs, points, atoms."""
+def orders(atom_xyz, basis, pts, point_atom, shell_order=None):
+    """Returns (ao_perm, pt_perm, atom_perm): internal index -> caller index for AOs, points, atoms.
+    shell_order: None (atom order) or the internal sequence of caller shell indices."""
     atom_xyz = np.asarray(atom_xyz, np.float64)
     pts = np.asarray(pts, np.float64)
     origin = origin_of(atom_xyz, pts)
@@ -67,9 +68,10 @@ def orders(atom_xyz, basis, pts, point_atom):
     ncart = np.array([(l + 1) * (l + 2) // 2 for l in basis.shell_l], np.int64)
     off = np.concatenate([[0], np.cumsum(ncart)[:-1]])
     ao = []
-    for a in aperm:
-        for s in np.nonzero(np.asarray(basis.shell_atom) == a)[0]:
-            ao.extend(range(off[s], off[s] + ncart[s]))
+    if shell_order is None:
+        shell_order = [s for a in aperm for s in np.nonzero(np.asarray(basis.shell_atom) == a)[0]]
+    for s in shell_order:
+        ao.extend(range(off[s], off[s] + ncart[s]))
     ao_perm = np.asarray(ao, np.int64)
     # points: primary key atom rank, secondary Morton key, stable
     q = discretise(pts, origin)

@@ -22,7 +22,7 @@ KLDI_OK = 0
 STATUS = {0: "KLDI_OK", -1: "KLDI_E_ARG", -2: "KLDI_E_OOM", -3: "KLDI_E_HIP", -4: "KLDI_E_UNSUPPORTED",
           -5: "KLDI_E_STATE", -6: "KLDI_E_NONFINITE"}
 XC = {"lda": 1, "pbe": 2, "pbe_x": 3}
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 3, "bf16x6": 4}
 SCHED = {"grid": 0, "queue": 1}
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -44,7 +44,7 @@ class kldi_opts(ctypes.Structure):
     _fields_ = [("t_b", ctypes.c_double), ("t_d", ctypes.c_double), ("rho_cut", ctypes.c_double),
                 ("grid_block", ctypes.c_int32), ("ao_block", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("xc", ctypes.c_int32), ("v_segment", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("shell_order", ctypes.c_void_p)]
 
 
 class kldi_plan_info_t(ctypes.Structure):
@@ -122,6 +122,11 @@ kldi_mlp_forward = _sig("kldi_mlp_forward", ctypes.c_int,
 kldi_mlp_loss_grad = _sig("kldi_mlp_loss_grad", ctypes.c_int,
                           [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                            ctypes.c_void_p, ctypes.c_void_p])
+kldi_mlp_step = _sig("kldi_mlp_step", ctypes.c_int,
+                     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                      ctypes.c_void_p, ctypes.c_void_p])
+kldi_overlap_order = _sig("kldi_overlap_order", ctypes.c_int,
+                          [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
 kldi_mlp_params = _sig("kldi_mlp_params", ctypes.c_int,
                        [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_void_p])
@@ -133,7 +138,7 @@ EXPORTS = sorted(["kldi_opts_default", "kldi_plan_create", "kldi_batch_create", 
                   "kldi_plan_graph", "kldi_plan_autotune", "kldi_plan_destroy", "kldi_plan_info",
                   "kldi_plan_structure", "kldi_eval", "kldi_eval_check", "kldi_plan_timing", "kldi_eval_timing",
                   "kldi_eval_grid", "kldi_xc_eval", "kldi_mlp_create", "kldi_mlp_destroy", "kldi_mlp_train",
-                  "kldi_mlp_forward", "kldi_mlp_loss_grad", "kldi_mlp_params", "kldi_plan_attach_mlp",
+                  "kldi_mlp_forward", "kldi_mlp_loss_grad", "kldi_mlp_step", "kldi_mlp_params", "kldi_overlap_order", "kldi_plan_attach_mlp",
                   "kldi_last_error", "kldi_version"])
 STAGES = ["dprep", "basis", "xgemm", "xfunc", "vgemm", "vfinal"]
 

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkldi.so")
-SOURCES = ["host.cpp", "mlp_host.cpp", "kernels.hip", "mlp.hip"]
+SOURCES = ["host.cpp", "mlp_host.cpp", "order.cpp", "kernels.hip", "mlp.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions stay off (wrong results have been seen from some forms)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -174,7 +174,9 @@ void validate_opts(const kldi_opts *o) {
   if (o->grid_block <= 0 || o->grid_block % 64 != 0) fail(KLDI_E_ARG, "grid_block must be a positive multiple of 64");
   if (o->grid_block != kG) fail(KLDI_E_UNSUPPORTED, "libkldi supports grid_block = 128");
   if (o->ao_block != kD) fail(KLDI_E_UNSUPPORTED, "libkldi supports ao_block = 32");
-  if (o->prec != KLDI_PREC_FP64 && o->prec != KLDI_PREC_FP32) fail(KLDI_E_ARG, "unknown prec");
+  if (o->prec != KLDI_PREC_FP64 && o->prec != KLDI_PREC_FP32 && o->prec != KLDI_PREC_BF16X3 &&
+      o->prec != KLDI_PREC_BF16X6)
+    fail(KLDI_E_ARG, "unknown prec");
   if (o->xc != KLDI_XC_LDA_X && o->xc != KLDI_XC_PBE && o->xc != KLDI_XC_PBE_X) fail(KLDI_E_ARG, "unknown xc");
   if (o->v_segment < 0) fail(KLDI_E_ARG, "v_segment must be >= 0");
   if (o->chunk_tiles < 0) fail(KLDI_E_ARG, "chunk_tiles must be >= 0");
@@ -224,7 +226,7 @@ struct MolPrep {
   std::vector<int64_t> cand_r;
 };
 
-void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, double t_b) {
+void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, double t_b, const int32_t *shell_seq) {
   const int na = b->n_atoms, ns = b->n_shells;
   const int64_t npt = g->n_points;
   M.n_points = npt;
@@ -262,8 +264,19 @@ void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, 
   std::vector<std::vector<int>> shells_of(na);
   for (int s = 0; s < ns; ++s) shells_of[b->shell_atom[s]].push_back(s);
   std::vector<int> shell_order;  // internal -> caller shell
-  for (int a : aorder)
-    for (int s : shells_of[a]) shell_order.push_back(s);
+  if (shell_seq) {
+    // a caller shell order (the overlap-signature reordering, kldi_overlap_order): a permutation
+    std::vector<char> seen(ns, 0);
+    for (int i = 0; i < ns; ++i) {
+      const int s = shell_seq[i];
+      if (s < 0 || s >= ns || seen[s]) fail(KLDI_E_ARG, "shell_order is not a permutation of the shells");
+      seen[s] = 1;
+      shell_order.push_back(s);
+    }
+  } else {
+    for (int a : aorder)
+      for (int s : shells_of[a]) shell_order.push_back(s);
+  }
 
   M.n_tiles = (M.n_ao + kD - 1) / kD;
   const int nao_pad = M.n_tiles * kD;
@@ -473,6 +486,9 @@ void make_queues(int64_t i0, int64_t i1, const std::vector<int64_t> &group_start
 }
 
 void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
+  if (schedule == KLDI_SCHED_QUEUE && P.n_blocks > kQueueMaxBlocks)
+    fail(KLDI_E_UNSUPPORTED, "the queue schedule is limited to plans of at most " + std::to_string(kQueueMaxBlocks) +
+                                 " grid blocks");
   free_list(P.sched_allocs);
   P.sched_bytes = 0;
   P.items_h.clear();
@@ -563,7 +579,8 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
 
   // grid chunks: whole segments whose retained tiles fit the Phi / Z workspaces
   const size_t esz = (P.opts.prec == KLDI_PREC_FP64) ? 8 : 4;
-  const size_t per_tile = 2 * 4096 * esz + (esz == 4 ? 4096 * 2 : 0);   // Phi + Z (+ bf16 low part of Phi)
+  // Phi + Z (+ bf16 low part of Phi) (+ the BF16 pieces of Phi for the X product)
+  const size_t per_tile = 2 * 4096 * esz + (esz == 4 ? 4096 * 2 : 0) + size_t(4096) * 2 * bf16_pieces(P.opts.prec);
   const size_t vfixed = P.items_h.size() * (16384 * 8 + 4);
   int64_t cap = chunk_tiles;
   {
@@ -675,6 +692,8 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
     E.zws = dev_alloc<float>(P, size_t(max_ret) * 4096, true);
     E.phil = dev_alloc<unsigned short>(P, size_t(max_ret) * 4096, true);
   }
+  const int npc = bf16_pieces(P.opts.prec);
+  E.phix = npc ? dev_alloc<unsigned short>(P, size_t(max_ret) * 4096 * npc, true) : nullptr;
   E.xpart = dev_alloc<double>(P, size_t(max_xit) * 4 * kG, true);
   E.vpart = dev_alloc<double>(P, P.items_h.size() * 16384, true);
   E.vflag = dev_alloc<int>(P, P.items_h.size(), true);
@@ -702,7 +721,7 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
     auto work = [&] {
       for (int m = next++; m < n_mol; m = next++) {
         try {
-          prepare_mol(mp[m], &bs[m], &gs[m], P.gga, o->t_b);
+          prepare_mol(mp[m], &bs[m], &gs[m], P.gga, o->t_b, o->shell_order);
         } catch (const Error &e) {
           codes[m] = e.code;
           errs[m] = e.msg;
@@ -917,7 +936,13 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
   // fixed workspaces
   const size_t esz = (o->prec == KLDI_PREC_FP64) ? 8 : 4;
   EvalDev &E = P.ev;
-  E.Dt = (esz == 8) ? (void *)dev_alloc<double>(P, size_t(P.n_dt) * 1024) : (void *)dev_alloc<float>(P, size_t(P.n_dt) * 1024);
+  const int npc = bf16_pieces(o->prec);
+  if (esz == 8)
+    E.Dt = dev_alloc<double>(P, size_t(P.n_dt) * 1024);
+  else if (npc)
+    E.Dt = dev_alloc<unsigned short>(P, size_t(P.n_dt) * 1024 * npc);
+  else
+    E.Dt = dev_alloc<float>(P, size_t(P.n_dt) * 1024);
   E.amax = dev_alloc<double>(P, size_t(P.n_dt));
   E.zmax = dev_alloc<double>(P, P.n_ret);
   E.coef = dev_alloc<double>(P, size_t(P.n_pad) * 4);
@@ -1056,6 +1081,7 @@ void kldi_opts_default(kldi_opts *o) {
   o->v_segment = 0;
   o->chunk_tiles = 0;
   o->schedule = KLDI_SCHED_GRID;
+  o->shell_order = nullptr;
 }
 
 kldi_status kldi_plan_create(const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts, void *stream,
@@ -1065,6 +1091,10 @@ kldi_status kldi_plan_create(const kldi_basis *basis, const kldi_grid *grid, con
 
 kldi_status kldi_batch_create(int32_t n_mol, const kldi_basis *basis, const kldi_grid *grid, const kldi_opts *opts,
                               void *stream, kldi_plan **out) {
+  if (opts && opts->shell_order && n_mol != 1) {
+    kldi::set_error("shell_order applies to single-molecule plans");
+    return KLDI_E_UNSUPPORTED;
+  }
   return kldi::create(n_mol, basis, grid, opts, stream, out);
 }
 
@@ -1303,6 +1333,7 @@ kldi_status kldi_plan_autotune(kldi_plan *plan, const double *D_dev, int32_t rep
       for (int seg : {8, 16, 32, 64}) {
         if (size_t(kldi::count_v_items(P, bc, seg)) * 16384 * 8 > budget) continue;
         for (int sched : {int(KLDI_SCHED_GRID), int(KLDI_SCHED_QUEUE)}) {
+          if (sched == KLDI_SCHED_QUEUE && P.n_blocks > kldi::kQueueMaxBlocks) continue;
           try {
             kldi::build_schedule(P, seg, sched, P.opts.chunk_tiles);
           } catch (const kldi::Error &e) {
@@ -1365,6 +1396,6 @@ kldi_status kldi_xc_eval(int32_t xc, const double *rho_dev, const double *sigma_
 
 const char *kldi_last_error(void) { return kldi::g_last_error.c_str(); }
 
-int32_t kldi_version(void) { return 2; }
+int32_t kldi_version(void) { return 3; }
 
 }  // extern "C"

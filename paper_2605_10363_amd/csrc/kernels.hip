@@ -124,19 +124,105 @@ __global__ __launch_bounds__(NT) void k_dprep(const MolDev *__restrict__ mol, in
   if (threadIdx.x == 0) amax[g] = fmax(fmax(s[0], s[1]), fmax(s[2], s[3]));
 }
 
+// BF16 split plans: the NPC BF16 pieces of each D element, v = v_0 + v_1 (+ v_2), piece k the BF16
+// rounding of what pieces 0 .. k-1 leave of v; tile g holds [piece][row i][column k].
+__device__ __forceinline__ void split_bf16(double v, int npc, unsigned short *out, size_t stride) {
+  double r = v;
+  for (int k = 0; k < npc; ++k) {
+    const unsigned short b = to_bf16(float(r));
+    out[k * stride] = b;
+    r -= from_bf16(b);
+  }
+}
+
+template <int NPC>
+__global__ __launch_bounds__(NT) void k_dprep_b(const MolDev *__restrict__ mol, int n_mol, const IoDev *io,
+                                               const int *__restrict__ perm, unsigned short *__restrict__ Dt,
+                                               double *__restrict__ amax, unsigned long long *counters) {
+  const int64_t g = blockIdx.x;
+  const MolDev mo = mol[find_mol(mol, n_mol, g, [](const MolDev &x) { return x.dt0; })];
+  const int loc = int(g - mo.dt0);
+  const int p = loc / mo.nt, q = loc % mo.nt, n_ao = mo.n_ao;
+  const double *D = io->D + mo.d0;
+  const int *pm = perm + size_t(mo.tile0) * kD;
+  double m = 0.0;
+  int bad = 0;
+  for (int e = threadIdx.x; e < kD * kD; e += NT) {
+    const int i = p * kD + e / kD, j = q * kD + e % kD;
+    double v = 0.0;
+    if (i < n_ao && j < n_ao) v = D[size_t(pm[i]) * n_ao + pm[j]];
+    if (!isfinite(v)) bad = 1;
+    m = fmax(m, fabs(v));
+    split_bf16(v, NPC, Dt + size_t(g) * (NPC * kD * kD) + e, kD * kD);
+  }
+  __shared__ double s[4];
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&counters[2], 1ull);
+  __syncthreads();
+  if (threadIdx.x == 0) amax[g] = fmax(fmax(s[0], s[1]), fmax(s[2], s[3]));
+}
+
 // FP32 operands also get Phi_lo = bf16(Phi - fl32(Phi)) (phil != NULL): the term the split product of
-// the Vxc GEMM adds back.
-template <class T>
+// the Vxc GEMM adds back.  BF16 split plans also get the NPC BF16 pieces of Phi in phix, per tile
+// [piece][point][AO] (the X product contracts over AOs).
+template <class T, int NPC>
 __global__ __launch_bounds__(kG) void k_basis(BasisDev B, GridDev g, StructDev st, int64_t ret0, T *__restrict__ phi,
-                                             unsigned short *__restrict__ phil) {
+                                             unsigned short *__restrict__ phil, unsigned short *__restrict__ phix) {
   const int64_t k = ret0 + blockIdx.x;     // retained tile; the workspace holds the chunk from ret0
   const int p = st.ret_p[k];
-  const int64_t ip = int64_t(st.ret_r[k]) * kG + threadIdx.x;
+  const int j = threadIdx.x;
+  const int64_t ip = int64_t(st.ret_r[k]) * kG + j;
   const double x = g.x[ip], y = g.y[ip], z = g.z[ip];
-  const size_t o = size_t(blockIdx.x) * (kD * kG) + threadIdx.x;
+  const size_t o = size_t(blockIdx.x) * (kD * kG) + j;
   T *out = phi + o;
   for (int a = B.tile_nv[p]; a < kD; ++a) out[a * kG] = T(0);
-  if (sizeof(T) == 4 && phil) {
+  if constexpr (NPC > 0) {
+    // this point's row of each piece, 16 bytes (8 AOs) at a time: the AOs of a tile arrive in
+    // increasing order (the same order in every thread), so a unit is stored once its last AO is in;
+    // units past the tile's AOs are zero
+    unsigned short *px = phix + size_t(blockIdx.x) * (NPC * kG * kD) + size_t(j) * kD;
+    uint32_t bw[NPC][4];
+    int cu = 0;
+    auto clear = [&]() {
+#pragma unroll
+      for (int c = 0; c < NPC; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bw[c][q] = 0u;
+    };
+    auto store = [&](int u) {
+#pragma unroll
+      for (int c = 0; c < NPC; ++c)
+        *reinterpret_cast<uint4 *>(px + c * (kG * kD) + 8 * u) = make_uint4(bw[c][0], bw[c][1], bw[c][2], bw[c][3]);
+    };
+    clear();
+    unsigned short *lo = phil + o;
+    for (int a = B.tile_nv[p]; a < kD; ++a) lo[a * kG] = 0;
+    for_tile_aos<false>(B, p, x, y, z, [&](int a, double v, double, double, double) {
+      while (cu < (a >> 3)) {
+        store(cu);
+        clear();
+        ++cu;
+      }
+      const T h = T(v);
+      out[a * kG] = h;
+      lo[a * kG] = to_bf16(float(v - double(h)));
+      const int q = (a & 7) >> 1, sh = 16 * (a & 1);
+      double rem = v;
+#pragma unroll
+      for (int c = 0; c < NPC; ++c) {
+        const unsigned short b = to_bf16(float(rem));
+        rem -= from_bf16(b);
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          if (qq == q) bw[c][qq] |= uint32_t(b) << sh;
+      }
+    });
+    for (; cu < 4; ++cu) {
+      store(cu);
+      clear();
+    }
+  } else if (sizeof(T) == 4 && phil) {
     unsigned short *lo = phil + o;
     for (int a = B.tile_nv[p]; a < kD; ++a) lo[a * kG] = 0;
     for_tile_aos<false>(B, p, x, y, z, [&](int a, double v, double, double, double) {
@@ -219,6 +305,7 @@ struct XArgs {
   const double *amax;
   const void *phi;
   const unsigned short *phil;   // FP32 operands: bf16(Phi - fl32(Phi)), else NULL
+  const unsigned short *phix;   // BF16 split plans: the BF16 pieces of Phi, [piece][point][AO] per tile
   double *part;            // [n_items][4][kG] rho, grad rho partial sums, indexed from item0
   unsigned long long *counters;
   double t_b, t_d;
@@ -232,7 +319,9 @@ constexpr int NTX = 512;   // threads per X workgroup: 8 waves, each 32 rows x 6
 // the 4 tiles p = S_r[4c .. 4c+3], then the chunk's contribution to rho and grad rho.  Wave w owns
 // tile 4c + (w & 3) and points 64 (w >> 2) .. 64 (w >> 2) + 63.
 // FP32 operands: MFMA accumulation spans one 32-AO K tile, the running sum is FP64.
-template <class T, bool GGA>
+// NPC > 0 (T = float): the operands are NPC BF16 pieces each, on BF16 MFMA (Dt holds D's pieces, phix
+// Phi's); the FP32 Phi serves the epilogue.
+template <class T, bool GGA, int NPC>
 __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   typedef Mma<T> M;
   typedef typename M::acc_t acc_t;
@@ -320,7 +409,90 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
       for (int v = 0; v < 4; ++v) dacc[ti][tj][v] = 0.0;
     }
   const bool has_u = 4 * c + u < np;
-  if constexpr (F32) {
+  if constexpr (NPC > 0) {
+    // ---- BF16 pieces.  Slot e % 2 holds entry e of the compacted list: the NPC pieces of the 4 D
+    // tiles (p_u, q), each [row i][k], then the NPC pieces of Phi_q, each [point][k]; a row is 64
+    // bytes, 4 units of 16 bytes, unit c of row i stored at c ^ ((i >> 1) & 3) (the 8 rows a
+    // 16-byte LDS read serves at once then fall on distinct banks).  Copies global -> LDS directly,
+    // one entry ahead, one barrier per entry.  v_mfma_f32_16x16x32_bf16: lane l supplies row (or
+    // point) 16 t + l % 16 at k = 8 (l / 16) .. + 7, one 16-byte read per piece and sub-tile; the
+    // products of pieces (a, b) with a + b <= NPC - 1 are added smallest first into the FP32
+    // accumulator of the K tile, which is then flushed to the FP64 sums.
+    constexpr int kTileB = kD * kD, kPhiB = kG * kD;
+    constexpr int kEntB = NPC * (4 * kTileB + kPhiB);     // bf16 elements per entry
+    constexpr int kPhiRounds = NPC * kPhiB / 8 / 64 / 4;   // 64-unit copies per Phi wave and entry
+    static_assert(2 * kEntB * 2 <= kStageBytes, "ring exceeds the staging area");
+    unsigned short *ring = reinterpret_cast<unsigned short *>(s_raw);
+    const int ws = __builtin_amdgcn_readfirstlane(w), us = ws & 3;
+    const int m16 = l & 15, g = l >> 4;
+    const unsigned short *Db = static_cast<const unsigned short *>(A.Dt);
+    const unsigned short *Pb = A.phix - size_t(A.ret0) * (NPC * kPhiB);   // indexed by retained tile
+    // D tile row of this wave's chunk entry (waves 0-3): an entry past the end of S_r uses entry np - 1
+    // (valid memory, never multiplied: its wave has no executable pair)
+    const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + us, np - 1)]);
+    const unsigned short *Drow = Db + dtile(pa, mo.tile0) * (NPC * kTileB);
+    auto issue = [&](int e) {
+      unsigned short *dst = ring + (e & 1) * kEntB;
+      if (ws < 4) {
+        const int q = __builtin_amdgcn_readfirstlane(s_q[e]);
+        const unsigned short *src = Drow + size_t(q - mo.tile0) * (NPC * kTileB);
+        dst += ws * (NPC * kTileB);
+#pragma unroll
+        for (int m = 0; m < 2 * NPC; ++m) {
+          const int du = 64 * m + l, pc = du >> 7, i = (du >> 2) & 31, cu = (du & 3) ^ ((i >> 1) & 3);
+          dma16(src + pc * kTileB + i * kD + 8 * cu, dst + 512 * m);
+        }
+      } else {
+        const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
+        const unsigned short *src = Pb + size_t(k0 + t) * (NPC * kPhiB);
+        const int u0 = (ws - 4) * (64 * kPhiRounds);
+        dst += NPC * 4 * kTileB;
+#pragma unroll
+        for (int m = 0; m < kPhiRounds; ++m) {
+          const int du = u0 + 64 * m + l, pc = du >> 9, i = (du >> 2) & 127, cu = (du & 3) ^ ((i >> 1) & 3);
+          dma16(src + pc * kPhiB + i * kD + 8 * cu, dst + 8 * (u0 + 64 * m));
+        }
+      }
+    };
+    auto rd = [&](const unsigned short *base, int i) {
+      return *reinterpret_cast<const bf16x8 *>(base + i * kD + 8 * (g ^ ((i >> 1) & 3)));
+    };
+    if (n_list > 0) issue(0);
+    for (int e = 0; e < n_list; ++e) {
+      wait_vm_lds<0>();
+      wg_barrier();
+      if (e + 1 < n_list) issue(e + 1);
+      if ((__builtin_amdgcn_readfirstlane(s_list[e] >> 16) >> us) & 1) {
+        const unsigned short *se = ring + (e & 1) * kEntB;
+        bf16x8 b[4][NPC];
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+          for (int pc = 0; pc < NPC; ++pc) b[tj][pc] = rd(se + NPC * 4 * kTileB + pc * kPhiB, 64 * h + 16 * tj + m16);
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti) {
+          bf16x8 a[NPC];
+#pragma unroll
+          for (int pc = 0; pc < NPC; ++pc) a[pc] = rd(se + us * (NPC * kTileB) + pc * kTileB, 16 * ti + m16);
+          // products by decreasing piece order: (2,0) (1,1) (0,2), then (1,0) (0,1), then (0,0)
+#pragma unroll
+          for (int ord = NPC - 1; ord >= 0; --ord)
+#pragma unroll
+            for (int pa_ = ord; pa_ >= 0; --pa_)
+#pragma unroll
+              for (int tj = 0; tj < 4; ++tj)
+                acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pa_], b[tj][ord - pa_], acc[ti][tj], 0, 0, 0);
+#pragma unroll
+          for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
+            acc[ti][tj] = acc_t{};
+          }
+        }
+      }
+    }
+    __syncthreads();
+  } else if constexpr (F32) {
     // ---- FP32 operands.  Slot S % kRing holds K step S: entries kPer S .. kPer S + kPer - 1 of the
     // compacted list, each the 4 D tiles (p_u, q) as [row i][k] with the 16-byte units of row i
     // XOR-swizzled (unit c at c ^ (i & 7)), then Phi_q as [k][point].  The copies go global -> LDS
@@ -499,7 +671,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
       for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          Xw[(16 * ti + M::row(v, l)) * kG + 64 * h + (F32 ? 4 * (l & 15) + tj : 16 * tj + (l & 15))] =
+          Xw[(16 * ti + M::row(v, l)) * kG + 64 * h + ((F32 && NPC == 0) ? 4 * (l & 15) + tj : 16 * tj + (l & 15))] =
               dacc[ti][tj][v] + double(acc[ti][tj][v]);
   }
   __syncthreads();
@@ -1110,7 +1282,7 @@ __global__ __launch_bounds__(NT) void k_esum(const MolDev *mol, const double *__
   if (threadIdx.x == 0) io->exc[blockIdx.x] = s[0];
 }
 
-template <class T>
+template <class T, int NPC>
 hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
   const EvalDev &E = P.ev;
   // stage events: per stage when the grid is processed in one chunk; with several chunks the
@@ -1120,7 +1292,11 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
     if (ev) (void)hipEventRecord(ev[i], s);
   };
   mark(0);
-  k_dprep<T><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, static_cast<T *>(E.Dt), E.amax, E.counters);
+  if constexpr (NPC > 0)
+    k_dprep_b<NPC><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, static_cast<unsigned short *>(E.Dt),
+                                         E.amax, E.counters);
+  else
+    k_dprep<T><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, static_cast<T *>(E.Dt), E.amax, E.counters);
   mark(1);
   if (!one) {
     mark(2);
@@ -1130,7 +1306,8 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
   for (size_t ci = 0; ci < P.chunks_h.size(); ++ci) {
     const GridChunk &C = P.chunks_h[ci];
     const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nxit = C.xit1 - C.xit0, nvit = C.vit1 - C.vit0;
-    if (nret > 0) k_basis<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, static_cast<T *>(E.phi), E.phil);
+    if (nret > 0)
+      k_basis<T, NPC><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, static_cast<T *>(E.phi), E.phil, E.phix);
     if (one) mark(2);
     XArgs xa;
     xa.B = P.basis;
@@ -1145,6 +1322,7 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
     xa.amax = E.amax;
     xa.phi = E.phi;
     xa.phil = E.phil;
+    xa.phix = E.phix;
     xa.part = E.xpart;
     xa.counters = E.counters;
     xa.t_b = P.opts.t_b;
@@ -1153,9 +1331,9 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
     const int64_t gx = 8 * P.xq.maxlen_h[ci];
     if (nxit > 0) {
       if (P.gga)
-        k_xgemm<T, true><<<gx, NTX, 0, s>>>(xa);
+        k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(xa);
       else
-        k_xgemm<T, false><<<gx, NTX, 0, s>>>(xa);
+        k_xgemm<T, false, NPC><<<gx, NTX, 0, s>>>(xa);
     }
     if (one) mark(3);
     FArgs fa;
@@ -1279,8 +1457,12 @@ hipError_t launch_begin(const Plan &P, const IoDev &io, hipStream_t s) {
 }
 
 hipError_t launch_body(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
-  if (P.opts.prec == KLDI_PREC_FP64) return body_typed<double>(P, want_v, s, ev);
-  return body_typed<float>(P, want_v, s, ev);
+  switch (P.opts.prec) {
+    case KLDI_PREC_FP64: return body_typed<double, 0>(P, want_v, s, ev);
+    case KLDI_PREC_BF16X3: return body_typed<float, 2>(P, want_v, s, ev);
+    case KLDI_PREC_BF16X6: return body_typed<float, 3>(P, want_v, s, ev);
+    default: return body_typed<float, 0>(P, want_v, s, ev);
+  }
 }
 
 }  // namespace kldi

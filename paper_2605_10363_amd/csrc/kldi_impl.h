@@ -15,17 +15,28 @@ constexpr int kG = 128;          // points per grid block
 constexpr int kD = 32;           // AOs per tile
 constexpr int kChunk = 4;        // AO tiles per workgroup row chunk (one per wave)
 constexpr int kMaxTilesPerBlock = 512;
+// Largest plan (in grid blocks) the queue schedule accepts.  A persistent form of that schedule
+// (workgroups pulling items from atomic counters) went silent on the GPU at the sizes of the 200-atom
+// chain and of eight batch molecules without a cause being found; the present one-workgroup-per-item
+// form has been run only on plans up to the 12-atom workload (413 blocks), so it stays within that class.
+constexpr int64_t kQueueMaxBlocks = 1024;
 constexpr int kMlpWidth = 64;       // hidden width of the functional surrogate
 constexpr int kMlpParams = 8707;    // 2-64-64-64-3 weights and biases
 
-// Device view of a trained functional surrogate.
+// BF16 pieces per operand of the X product (0: the plan's operands are FP64 or FP32)
+inline int bf16_pieces(int prec) { return prec == KLDI_PREC_BF16X3 ? 2 : (prec == KLDI_PREC_BF16X6 ? 3 : 0); }
+
+// Device view of a trained functional surrogate.  Every field points into the network's own device
+// memory, which training updates in place, so a plan (or a captured graph) holding the view always
+// reads the current parameters and statistics.
 struct MlpDev {
   const unsigned short *theta_b;  // [kMlpParams] BF16 weights (inference)
   const float *bias;              // [kMlpParams] FP32 master parameters (biases read from here)
-  double box[4];                  // training range of log rho and log sigma
-  double tmean[3], tstd[3];       // target standardisation
-  double rho_min;                 // below this density the analytic functional is used
+  const double *stats;            // [kMlpStats]: box[4] (training range of log rho, log sigma),
+                                  // tmean[3], tstd[3] (target standardisation), rho_min (below it
+                                  // the analytic functional is used)
 };
+constexpr int kMlpStats = 11;
 
 // A plan holds one molecule or a batch of independent molecules in one index space: the AO tiles,
 // grid blocks, retained tiles and work items of all molecules are numbered consecutively, and every
@@ -87,11 +98,13 @@ struct StructDev {
 };
 
 struct EvalDev {
-  void *Dt;                // [sum nt^2 * 1024] internal tiled D, working precision
+  void *Dt;                // [sum nt^2 * 1024] internal tiled D, working precision (BF16 split plans:
+                           // [sum nt^2][piece][1024] BF16 pieces)
   double *amax;            // [sum nt^2] max |D_pq|
   void *phi;               // [max chunk retained tiles * 4096] Phi workspace, working precision
   void *zws;               // [max chunk retained tiles * 4096] Z workspace
   unsigned short *phil;    // FP32 plans: [max chunk retained tiles * 4096] bf16(Phi - fl32(Phi)); else NULL
+  unsigned short *phix;    // BF16 split plans: per retained tile the BF16 pieces of Phi, [piece][point][AO]
   double *xpart;           // [max chunk X items * 4 * 128] rho / grad rho partials of each X work item
   double *coef;            // [n_pad * 4] Z coefficients per point
   double *zmax;            // [n_ret]

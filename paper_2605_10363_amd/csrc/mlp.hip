@@ -398,10 +398,11 @@ __device__ void mlp_block(const MlpDev &m, const float (*xs)[2], float (*ys)[3],
 
 // features of one point; false when the network does not cover it
 __device__ __forceinline__ bool mlp_features(const MlpDev &m, double rho, double sigma, float *x) {
-  if (!(rho >= m.rho_min)) return false;
+  const double *box = m.stats;
+  if (!(rho >= m.stats[10])) return false;
   const double lr = log(rho), ls = log(fmax(sigma, 1e-30));
-  const double x0 = 2.0 * (lr - m.box[0]) / (m.box[1] - m.box[0]) - 1.0;
-  const double x1 = 2.0 * (ls - m.box[2]) / (m.box[3] - m.box[2]) - 1.0;
+  const double x0 = 2.0 * (lr - box[0]) / (box[1] - box[0]) - 1.0;
+  const double x1 = 2.0 * (ls - box[2]) / (box[3] - box[2]) - 1.0;
   x[0] = float(x0);
   x[1] = float(x1);
   return x0 >= -1.0 && x0 <= 1.0 && x1 >= -1.0 && x1 <= 1.0;
@@ -409,9 +410,10 @@ __device__ __forceinline__ bool mlp_features(const MlpDev &m, double rho, double
 
 __device__ __forceinline__ Xc mlp_output(const MlpDev &m, double rho, const float *y) {
   const double r13 = cbrt(rho), r43 = rho * r13;
-  const double t0 = double(y[0]) * m.tstd[0] + m.tmean[0];
-  const double t1 = double(y[1]) * m.tstd[1] + m.tmean[1];
-  const double t2 = double(y[2]) * m.tstd[2] + m.tmean[2];
+  const double *tmean = m.stats + 4, *tstd = m.stats + 7;
+  const double t0 = double(y[0]) * tstd[0] + tmean[0];
+  const double t1 = double(y[1]) * tstd[1] + tmean[1];
+  const double t2 = double(y[2]) * tstd[2] + tmean[2];
   return Xc{t0 * r43, t1 * r13, t2 / r43};
 }
 

@@ -11,6 +11,7 @@ struct kldi_mlp {
   int device = 0;
   float *theta = nullptr, *m = nullptr, *v = nullptr;  // [kMlpParams] FP32 master, Adam moments
   unsigned short *theta_b = nullptr;                    // [kMlpParams] BF16 copy
+  double *stats = nullptr;                              // [kMlpStats] device copy of box, tmean, tstd, rho_min
   double box[4] = {0, 1, 0, 1};
   double tmean[3] = {0, 0, 0}, tstd[3] = {1, 1, 1};
   double rho_min = 1e-8;
@@ -69,13 +70,27 @@ kldi::MlpDev view(const kldi_mlp &M) {
   kldi::MlpDev d;
   d.theta_b = M.theta_b;
   d.bias = M.theta;
-  for (int i = 0; i < 4; ++i) d.box[i] = M.box[i];
-  for (int i = 0; i < 3; ++i) {
-    d.tmean[i] = M.tmean[i];
-    d.tstd[i] = M.tstd[i];
-  }
-  d.rho_min = M.rho_min;
+  d.stats = M.stats;
   return d;
+}
+
+// the host statistics in the device layout of MlpDev::stats
+void stats_to_device(const kldi_mlp &M, hipStream_t s) {
+  double h[kldi::kMlpStats];
+  for (int i = 0; i < 4; ++i) h[i] = M.box[i];
+  for (int i = 0; i < 3; ++i) {
+    h[4 + i] = M.tmean[i];
+    h[7 + i] = M.tstd[i];
+  }
+  h[10] = M.rho_min;
+  hipc(hipMemcpyAsync(M.stats, h, sizeof(h), hipMemcpyHostToDevice, s), "copy");
+  hipc(hipStreamSynchronize(s), "sync");
+}
+
+bool require_trained(const kldi_mlp *M) {
+  if (M->trained) return true;
+  kldi::set_error("the network has not been trained (kldi_mlp_train)");
+  return false;
 }
 
 }  // namespace
@@ -96,6 +111,7 @@ kldi_status kldi_mlp_create(const kldi_mlp_cfg *cfg, kldi_mlp **out) {
     M->m = dalloc<float>(kldi::kMlpParams, keep);
     M->v = dalloc<float>(kldi::kMlpParams, keep);
     M->theta_b = dalloc<unsigned short>(kldi::kMlpParams, keep);
+    M->stats = dalloc<double>(kldi::kMlpStats, keep);
     // U(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases, in the documented order
     std::vector<float> th(kldi::kMlpParams, 0.f);
     uint64_t s = cfg->seed;
@@ -117,6 +133,7 @@ kldi_status kldi_mlp_create(const kldi_mlp_cfg *cfg, kldi_mlp **out) {
     hipc(hipMemcpy(M->v, zero.data(), zero.size() * 4, hipMemcpyHostToDevice), "copy");
     hipc(kldi::mlp_launch_tobf16(M->theta, M->theta_b, nullptr), "bf16");
     hipc(hipDeviceSynchronize(), "sync");
+    stats_to_device(*M, nullptr);
   });
   if (st != KLDI_OK) {
     for (void *q : keep) (void)hipFree(q);
@@ -131,7 +148,8 @@ kldi_status kldi_mlp_destroy(kldi_mlp *M) {
   if (!M) return KLDI_OK;
   (void)hipSetDevice(M->device);
   (void)hipDeviceSynchronize();
-  for (void *p : {(void *)M->theta, (void *)M->m, (void *)M->v, (void *)M->theta_b}) (void)hipFree(p);
+  for (void *p : {(void *)M->theta, (void *)M->m, (void *)M->v, (void *)M->theta_b, (void *)M->stats})
+    (void)hipFree(p);
   delete M;
   return KLDI_OK;
 }
@@ -179,6 +197,34 @@ kldi_status kldi_mlp_loss_grad(kldi_mlp *M, const float *x, const float *t, int6
     hipc(hipMemcpyAsync(&l, lsum, 8, hipMemcpyDeviceToHost, s), "copy");
     hipc(hipStreamSynchronize(s), "sync");
     *loss = l / (3.0 * double(n));
+  });
+  for (void *q : keep) (void)hipFree(q);
+  return st;
+}
+
+kldi_status kldi_mlp_step(kldi_mlp *M, const float *x, const float *t, int64_t n, double lr, double *loss,
+                          void *stream) {
+  if (!M || !x || !t || n < 1 || n > (1 << 20) || !(lr > 0)) {
+    kldi::set_error("bad arguments to kldi_mlp_step");
+    return KLDI_E_ARG;
+  }
+  std::vector<void *> keep;
+  kldi_status st = run([&] {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipc(hipSetDevice(M->device), "hipSetDevice");
+    const int nwg = int((n + 63) / 64);
+    float *gpart = dalloc<float>(size_t(nwg) * kldi::kMlpParams, keep);
+    double *lpart = dalloc<double>(nwg, keep);
+    double *lsum = dalloc<double>(1, keep);
+    hipc(hipMemsetAsync(lsum, 0, 8, s), "memset");
+    hipc(kldi::mlp_launch_grad(M->theta, x, t, n, 0, n, 1, 0, gpart, lpart, s), "grad");
+    ++M->step;
+    hipc(kldi::mlp_launch_adam(M->theta, M->m, M->v, M->theta_b, gpart, nwg, float(lr), M->step, nullptr, s), "adam");
+    hipc(kldi::mlp_launch_loss_sum(lpart, nwg, lsum, s), "loss");
+    double l = 0;
+    hipc(hipMemcpyAsync(&l, lsum, 8, hipMemcpyDeviceToHost, s), "copy");
+    hipc(hipStreamSynchronize(s), "sync");
+    if (loss) *loss = l / (3.0 * double(n));
   });
   for (void *q : keep) (void)hipFree(q);
   return st;
@@ -281,6 +327,7 @@ kldi_status kldi_mlp_train(kldi_mlp *M, const double *rho, const double *sigma, 
     M->rho_min = cfg->rho_min;
     M->xc = cfg->xc;
     M->trained = true;
+    stats_to_device(*M, s);
   });
   for (void *q : keep) (void)hipFree(q);
   return st;
@@ -292,6 +339,7 @@ kldi_status kldi_mlp_forward(const kldi_mlp *M, const double *rho, const double 
     kldi::set_error("bad arguments to kldi_mlp_forward");
     return KLDI_E_ARG;
   }
+  if (!require_trained(M)) return KLDI_E_STATE;
   return run([&] {
     hipc(hipSetDevice(M->device), "hipSetDevice");
     hipc(kldi::mlp_launch_forward(view(*M), rho, sigma, n, M->xc, f, vr, vs, used, static_cast<hipStream_t>(stream)),
@@ -307,6 +355,11 @@ kldi_status kldi_plan_attach_mlp(kldi_plan *plan, const kldi_mlp *M) {
   if (M && plan->impl.opts.xc == KLDI_XC_LDA_X) {
     kldi::set_error("the surrogate replaces a GGA functional; this plan is LDA");
     return KLDI_E_UNSUPPORTED;
+  }
+  if (M && !require_trained(M)) return KLDI_E_STATE;
+  if (M && M->xc != plan->impl.opts.xc) {
+    kldi::set_error("the network was trained on another functional than the plan's");
+    return KLDI_E_ARG;
   }
   plan->impl.has_mlp = M != nullptr;
   if (M) plan->impl.mlp = view(*M);

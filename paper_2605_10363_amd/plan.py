@@ -122,11 +122,16 @@ class Plan(_PlanBase):
 
     def __init__(self, atom_xyz, basis, grid_xyz, weights, point_atom, xc="lda", prec="fp64", t_b=1e-10,
                  t_d=1e-10, rho_cut=1e-14, grid_block=128, ao_block=32, v_segment=0, chunk_tiles=0, schedule="grid",
-                 stream=None):
+                 shell_order=None, stream=None):
+        """shell_order: None (atom order) or the internal sequence of shells (e.g. overlap_order())."""
         self._h = ctypes.c_void_p()
         self._keep = []
         b, g, self.n_ao, self.n_points = _structs(atom_xyz, basis, grid_xyz, weights, point_atom, self._keep)
         o = _opts(xc, prec, t_b, t_d, rho_cut, grid_block, ao_block, v_segment, chunk_tiles, schedule)
+        if shell_order is not None:
+            so = np.ascontiguousarray(shell_order, np.int32)
+            self._keep.append(so)
+            o.shell_order = so.ctypes.data
         self.xc, self.prec = xc, prec
         L.check(L.kldi_plan_create(ctypes.byref(b), ctypes.byref(g), ctypes.byref(o), _stream_handle(stream),
                                    ctypes.byref(self._h)), "kldi_plan_create")
@@ -229,6 +234,22 @@ def xc_eval(xc, rho, sigma=None, rho_cut=0.0, stream=None):
     return f, vr, vs
 
 
+def overlap_order(basis, S):
+    """kldi_overlap_order: (leaf order of the AOs, shell order) from the overlap matrix S (caller order)."""
+    sl = np.ascontiguousarray(basis.shell_l, np.int32)
+    n_ao = int(sum((int(l) + 1) * (int(l) + 2) // 2 for l in sl))
+    S = np.ascontiguousarray(S, np.float64)
+    if S.shape != (n_ao, n_ao):
+        raise ValueError("S must be n_ao x n_ao")
+    b = L.kldi_basis()
+    b.n_shells = sl.shape[0]
+    b.shell_l = sl.ctypes.data
+    ao = np.empty(n_ao, np.int32)
+    so = np.empty(sl.shape[0], np.int32)
+    L.check(L.kldi_overlap_order(ctypes.byref(b), S.ctypes.data, ao.ctypes.data, so.ctypes.data), "kldi_overlap_order")
+    return ao, so
+
+
 class Mlp:
     """kldi_mlp_*: the functional surrogate (2-64-64-64-3 SiLU), trained and run by libkldi."""
 
@@ -258,6 +279,13 @@ class Mlp:
         L.check(L.kldi_mlp_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()), x.shape[0],
                                      ctypes.byref(loss), g.ctypes.data, _stream_handle(stream)), "kldi_mlp_loss_grad")
         return loss.value, g
+
+    def step(self, x, t, lr, stream=None):
+        """One Adam step on the batch (x, t) (float32 CUDA [n, 2], [n, 3]); returns the loss before it."""
+        loss = ctypes.c_double()
+        L.check(L.kldi_mlp_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()), x.shape[0],
+                                float(lr), ctypes.byref(loss), _stream_handle(stream)), "kldi_mlp_step")
+        return loss.value
 
     def train(self, rho, sigma, epochs=10, batch=65536, lr=2e-3, seed=1, xc="pbe", rho_min=1e-8, stream=None):
         cfg = L.kldi_train_cfg(int(epochs), int(batch), float(lr), int(seed), L.XC[xc], float(rho_min))

@@ -515,6 +515,51 @@ def make_problem(k: int, cache=True) -> Problem:
     return p
 
 
+def subset_problem(k: int, n_sub=200, G=128, cache=True) -> Problem:
+    """The n_sub atoms of cluster workload k nearest its centroid, as a problem of their own.
+
+    Geometry and basis are those of workload k (same seeds): the selected atoms keep their positions
+    and shells, in their order in the cluster.  The grid (the recipe's radial x angular points, Becke
+    partition over the subset) and D (orbital seed 3100+k, round(N_AO/5) occupied orbitals, the
+    occupied-orbital ratio of the recipe) are built for the subset alone.  Ties in the distance are
+    broken by atom index.
+    """
+    recipe = RECIPES[k]
+    if recipe["kind"] != "sphere":
+        raise ValueError("subset_problem: workload %d is not a cluster" % k)
+    seeds = (1000 + k, 2000 + k, 3100 + k)
+    meta = dict(recipe=dict(recipe), seeds=list(seeds), generator=GENERATOR_VERSION,
+                subset=dict(of=k, n_atoms=n_sub, rule="nearest to the centroid"))
+    key = hashlib.sha1(repr((GENERATOR_VERSION, sorted(recipe.items()), seeds, n_sub, G)).encode()).hexdigest()[:16]
+    path = os.path.join(_cache_dir(), "cfg%dsub%d_%s.npz" % (k, n_sub, key))
+    if cache and os.path.exists(path):
+        return _load(path, meta)
+    xyz, heavy = sphere_cluster(np.random.default_rng(seeds[0]), recipe["n_heavy"], recipe["n_light"])
+    full = make_basis(np.random.default_rng(seeds[1]), heavy)
+    d = np.linalg.norm(xyz - xyz.mean(axis=0), axis=1)
+    sel = np.sort(np.lexsort((np.arange(len(d)), d))[:n_sub])
+    new_index = -np.ones(len(xyz), np.int64)
+    new_index[sel] = np.arange(n_sub)
+    keep = np.flatnonzero(new_index[full.shell_atom] >= 0)
+    ptr, exps, coefs = [0], [], []
+    for s in keep:
+        a0, a1 = full.prim_ptr[s], full.prim_ptr[s + 1]
+        exps.extend(full.prim_exp[a0:a1].tolist())
+        coefs.extend(full.prim_coef[a0:a1].tolist())
+        ptr.append(len(exps))
+    basis = Basis(new_index[full.shell_atom[keep]].astype(np.int32), full.shell_l[keep].astype(np.int32),
+                  np.asarray(ptr, np.int32), np.asarray(exps, np.float64), np.asarray(coefs, np.float64))
+    sxyz = xyz[sel]
+    grid = make_grid(sxyz, recipe["n_rad"], recipe["n_ang"], recipe.get("becke_cutoff", 0.0))
+    n_occ = int(round(basis.n_ao / 5.0))
+    D = make_density(np.random.default_rng(seeds[2]), overlap_matrix(basis, sxyz), n_occ)
+    p = Problem(name="cfg%dsub%d" % (k, n_sub), atom_xyz=sxyz, atom_heavy=heavy[sel], basis=basis, grid=grid,
+                D=D, n_occ=n_occ, xc=recipe["xc"], grid_block=G, meta=meta)
+    if cache:
+        _save(p, path)
+    return p
+
+
 def tiny_problem(n_atoms=3, n_rad=12, n_ang=26, n_occ=3, xc="lda", seed=7, heavy=None, box_A=3.0, G=128):
     """Small seeded problem for unit tests (ragged AO count and grid length by construction)."""
     n_heavy = (n_atoms + 1) // 2 if heavy is None else heavy

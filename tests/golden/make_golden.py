@@ -6,7 +6,14 @@ diagonal), drawn from numpy's default_rng(12345).
   cfg1_oracle.json   200-atom chain, PBE: dense (unscreened) evaluation, oracle.eval_exc
   cfg1_blocked.json  the same problem with the block filter at t_b = t_d = 1e-10, d = 32, G = 128,
                      oracle.blocked.eval_blocked_stream (the method's own result at those thresholds)
-Run from the repository root:  python tests/golden/make_golden.py [dense|blocked]
+  cfg2sub_blocked.json  the 200 atoms of the 1000-atom cluster nearest its centroid (synth.subset_problem:
+                     1970 AOs, 4.53M points, own grid and D), PBE, block-filtered at 1e-10, d = 32, G = 128
+  member_blocked.json   the largest molecule of the 256-molecule batch (synth.make_batch), PBE,
+                     block-filtered at 1e-10, d = 32, G = 128
+  cfg1_overlap_blocked.json  the 200-atom chain block-filtered at 1e-10 with the basis functions ordered by
+                     overlap-signature clustering (oracle.cluster, shell order from the analytic overlap
+                     matrix of synth)
+Run from the repository root:  python tests/golden/make_golden.py [dense|blocked|cfg2sub|member|overlap]
 """
 import json
 import os
@@ -45,7 +52,7 @@ def dense(p):
     }
 
 
-def blocked(p, t=1e-10):
+def blocked(p, t=1e-10, label="cfg1: 200-atom chain, 2000 AOs, 4.53M points, PBE", shell_order=None):
     pts, ij = samples(p)
     diag = np.stack([np.arange(p.n_ao)] * 2, 1)
     t0 = time.time()
@@ -56,12 +63,12 @@ def blocked(p, t=1e-10):
 
     r = oracle.blocked.eval_blocked_stream(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom,
                                            p.D, p.xc, t_b=t, t_d=t, d_ao=32, G=128,
-                                           v_entries=np.concatenate([ij, diag]), progress=prog)
+                                           v_entries=np.concatenate([ij, diag]), progress=prog,
+                                           shell_order=shell_order)
     dt = time.time() - t0
     v = r["v"]
     return {
-        "workload": "cfg1: 200-atom chain, 2000 AOs, 4.53M points, PBE, block-filtered FP64 oracle "
-                    "(t_b = t_d = %g, d = 32, G = 128)" % t,
+        "workload": label + ", block-filtered FP64 oracle (t_b = t_d = %g, d = 32, G = 128)" % t,
         "t_b": t, "t_d": t, "generator": synth.GENERATOR_VERSION, "seeds": p.meta["seeds"], "oracle_seconds": dt,
         "E": r["E"], "electrons": float(p.grid.weight @ r["rho"]), "n_occ": p.n_occ,
         "n_pairs_x": r["nP_X"], "n_pairs_v": r["nP_M"],
@@ -70,12 +77,44 @@ def blocked(p, t=1e-10):
     }
 
 
+def largest_member():
+    """Index and problem of the largest molecule of the batching workload, with the PBE functional."""
+    sizes = synth.batch_sizes()
+    j = int(np.argmax(sizes))
+    mols = synth.make_batch(n_mol=j + 1, xc="pbe")
+    return j, mols[j]
+
+
 def main():
     which = sys.argv[1:] or ["dense", "blocked"]
-    p = synth.make_problem(1)
     for w in which:
-        out = dense(p) if w == "dense" else blocked(p)
-        path = os.path.join(ROOT, "tests", "golden", "cfg1_oracle.json" if w == "dense" else "cfg1_blocked.json")
+        if w in ("dense", "blocked"):
+            p = synth.make_problem(1)
+            out = dense(p) if w == "dense" else blocked(p)
+            name = "cfg1_oracle.json" if w == "dense" else "cfg1_blocked.json"
+        elif w == "cfg2sub":
+            p = synth.subset_problem(2)
+            out = blocked(p, label="cfg2 subset: the 200 atoms of the 1000-atom cluster nearest its centroid, "
+                                   "%d AOs, %d points, PBE" % (p.n_ao, p.n_points))
+            out["subset"] = p.meta["subset"]
+            name = "cfg2sub_blocked.json"
+        elif w == "overlap":
+            from oracle import cluster
+            p = synth.make_problem(1)
+            so, _ = cluster.overlap_shell_order(synth.overlap_matrix(p.basis, p.atom_xyz), p.basis, lib=True)
+            out = blocked(p, label="cfg1: 200-atom chain, 2000 AOs, 4.53M points, PBE, basis functions ordered by "
+                                   "overlap-signature clustering", shell_order=so)
+            out["shell_order"] = so.tolist()
+            name = "cfg1_overlap_blocked.json"
+        elif w == "member":
+            j, p = largest_member()
+            out = blocked(p, label="batch member %d (%d atoms, %d AOs, %d points), PBE" % (
+                j, p.n_atoms, p.n_ao, p.n_points))
+            out["member"] = j
+            name = "member_blocked.json"
+        else:
+            raise SystemExit("unknown golden %r" % w)
+        path = os.path.join(ROOT, "tests", "golden", name)
         with open(path, "w") as f:
             json.dump(out, f)
         print("wrote", path, "E =", out["E"], "in %.0f s" % out["oracle_seconds"], flush=True)

@@ -177,7 +177,8 @@ def _check_workload_members(mod, schedule):
 @pytest.mark.skip(reason="a GPU run of this case (queue schedule, then persistent workgroups pulling items from "
                          "atomic counters) went silent for 180 s and was stopped, as did the 200-atom chain under that "
                          "schedule; reading the code and a CPU build that walks every kernel index found no cause, so "
-                         "the case stays off the GPU until one is shown")
+                         "the case stays off the GPU until one is shown (the library now refuses the queue schedule "
+                         "above 1024 grid blocks, which this batch exceeds)")
 def test_batch_of_workload_members_against_oracle(mod):
     _check_workload_members(mod, "queue")
 

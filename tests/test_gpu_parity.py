@@ -149,7 +149,8 @@ def test_rho_only_and_no_vxc(Plan):
     plan.close()
 
 
-@pytest.mark.parametrize("xc,prec", [("lda", "fp64"), ("pbe", "fp64"), ("lda", "fp32"), ("pbe", "fp32")])
+@pytest.mark.parametrize("xc,prec", [("lda", "fp64"), ("pbe", "fp64"), ("lda", "fp32"), ("pbe", "fp32"),
+                                     ("pbe", "bf16x6")])
 def test_grid_chunks_give_identical_results(Plan, cfg0, xc, prec):
     """Processing the grid in several chunks of whole Vxc segments (small Phi/Z workspaces) must give
     bit-identical results to one chunk: the same work items run, and every sum keeps its order.  With FP32
@@ -171,7 +172,7 @@ def test_grid_chunks_give_identical_results(Plan, cfg0, xc, prec):
     assert (sa["n_pairs_x"], sa["n_pairs_v"]) == (sb["n_pairs_x"], sb["n_pairs_v"])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x3"])
 def test_zero_density_matrix_gives_exact_zeros(Plan, prec):
     """D = 0: every a_pq is 0, so no (p, q) pair is executable (eq. block_pair_filter); rho = 0 gives
     f = v = 0 below the density floor, so Z, every Vxc pair and Vxc vanish.  The oracle gives the same
@@ -192,7 +193,7 @@ def test_zero_density_matrix_gives_exact_zeros(Plan, prec):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 def test_thresholds_that_retain_nothing(Plan, prec):
     """t_b = t_d = 1e300: no (tile, block) pair is retained (eq. retained_blocks_B), so the plan has no X or
     Vxc work items; every output is an exact zero, as in the oracle at the same thresholds."""
@@ -219,7 +220,79 @@ def test_grid_smaller_than_one_block(Plan, xc):
     assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * np.abs(ref["rho"]).max()
     assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
     g["plan"].close()
-    f = run(Plan, p, xc, prec="fp32")
-    assert abs(f["E"] - ref["E"]) < 1e-6 and np.abs(f["V"] - ref["V"]).max() < 1e-7
-    assert np.array_equal(f["V"], f["V"].T)
-    f["plan"].close()
+    for prec in ("fp32", "bf16x6"):
+        f = run(Plan, p, xc, prec=prec)
+        assert abs(f["E"] - ref["E"]) < 1e-6 and np.abs(f["V"] - ref["V"]).max() < 1e-7
+        assert np.array_equal(f["V"], f["V"].T)
+        f["plan"].close()
+
+
+def _rho_abs(p):
+    """sum_{mu nu} |Phi_mu,i| |D_mu nu| |Phi_nu,i| per point (dense oracle basis): the scale that bounds the
+    rounding of rho = sum_{mu nu} Phi_mu,i D_mu nu Phi_nu,i whatever the signs of its terms."""
+    from oracle import basis as obasis
+    phi = obasis.eval_ao(p.atom_xyz, p.basis, p.grid.xyz, deriv=0)
+    a = np.abs(phi[0] if isinstance(phi, tuple) else phi)
+    return np.einsum("mi,mi->i", a, np.abs(p.D) @ a)
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+@pytest.mark.parametrize("shape", TINY + [None])
+def test_split_bf16_forms_against_blocked_oracle(Plan, cfg0, prec, xc, shape):
+    """The split-precision X product on BF16 MFMA against the blocked FP64 oracle.  With k pieces per
+    operand each of D and Phi is represented to 2^(-8k) relative and the dropped products are of that
+    order, so every term Phi_p D_pq Phi_q of rho carries a relative error below 3 * 2^(-8k); FP32
+    accumulation of the 32-term products of a K tile and their FP64 flushes add at most 34 * 2^-24 of
+    the terms' magnitudes.  Hence |rho - rho_ref| <= (3 * 2^(-8k) + 34 * 2^-24) sum |Phi||D||Phi| per
+    point.  Six products (k = 3) also meet the precision targets of the mixed form (1e-6 Eh in E_xc,
+    1e-7 in Vxc); three (k = 2) are reported."""
+    if shape is None:
+        p = cfg0
+    else:
+        n_atoms, n_rad, n_ang, n_occ, seed = shape
+        p = synth.tiny_problem(n_atoms=n_atoms, n_rad=n_rad, n_ang=n_ang, n_occ=n_occ, xc=xc, seed=seed, box_A=4.0)
+    ref = blocked_ref(p, xc)
+    g = run(Plan, p, xc, prec=prec)
+    k = 3 if prec == "bf16x6" else 2
+    bound = (3 * 2.0 ** (-8 * k) + 34 * 2.0 ** -24) * _rho_abs(p)
+    drho = np.abs(g["rho"] - ref["rho"])
+    dE = abs(g["E"] - ref["E"])
+    dV = np.abs(g["V"] - ref["V"]).max()
+    print("%s %s %s: dE %.3e dV %.3e max drho/bound %.3f" % (p.name, xc, prec, dE, dV, (drho / bound).max()),
+          flush=True)
+    assert np.all(drho <= bound)
+    assert np.array_equal(g["V"], g["V"].T)
+    assert g["stats"]["n_pairs_x"] == ref["nP_X"]
+    if prec == "bf16x6":
+        assert dE < 1e-6 and dV < 1e-7
+    g["plan"].close()
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+@pytest.mark.parametrize("which", ["tiny", "cfg0"])
+def test_overlap_clustered_basis_order(Plan, cfg0, xc, which):
+    """Plans whose basis functions follow the overlap-signature clustering (kldi_overlap_order, shell
+    order in kldi_opts) against the blocked oracle run with the same shell order (oracle.cluster): FP64 to
+    1e-12 with identical executed pair counts, and identical internal AO orders."""
+    from paper_2605_10363_amd.plan import overlap_order
+    from oracle import cluster
+    p = cfg0 if which == "cfg0" else synth.tiny_problem(n_atoms=5, n_rad=14, n_ang=38, n_occ=5, xc=xc, seed=45,
+                                                        box_A=5.0)
+    S = synth.overlap_matrix(p.basis, p.atom_xyz)
+    so_ref, _ = cluster.overlap_shell_order(S, p.basis)
+    _, so = overlap_order(p.basis, S)
+    assert np.array_equal(so, so_ref)
+    ref = oracle.eval_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc,
+                              t_b=1e-10, t_d=1e-10, d_ao=32, G=128, shell_order=so_ref)
+    g = run(Plan, p, xc, shell_order=so)
+    ao, _, _, _ = g["plan"].structure()
+    assert np.array_equal(ao, ref["ao_perm"])
+    assert abs(g["E"] - ref["E"]) <= 1e-12 * max(1.0, abs(ref["E"]))
+    assert np.abs(g["V"] - ref["V"]).max() <= 1e-12 * max(1.0, np.abs(ref["V"]).max())
+    assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * max(1.0, np.abs(ref["rho"]).max())
+    assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
+    print("%s %s: retained fraction %.4f (atom order %.4f)" % (which, xc, g["info"]["retained_fraction"],
+                                                             Plan.from_problem(p, xc=xc).info()["retained_fraction"]),
+          flush=True)
+    g["plan"].close()

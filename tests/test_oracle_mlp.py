@@ -72,3 +72,38 @@ def test_training_reduces_loss_on_a_smooth_target():
         L, g = mlp.loss_and_grad(th, x, s)
         th, m, v = mlp.adam_step(th, g, m, v, k, lr=3e-3)
     assert mlp.loss_and_grad(th, x, s)[0] < 0.1 * L0
+
+
+def test_bf16_round_known_values():
+    # 8 significant bits: 1 + 2^-8 is halfway between 1 and 1 + 2^-7 and ties to the even 1;
+    # 1 + 3*2^-8 ties to the even 1 + 2^-6; 1 + 2^-8 + 2^-20 rounds up
+    v = mlp.bf16_round(np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -8 + 2.0 ** -20, -3.0, 0.0]))
+    assert np.array_equal(v, [1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -3.0, 0.0])
+    r = np.random.default_rng(0).normal(size=10000) * 10.0 ** np.random.default_rng(1).uniform(-5, 5, 10000)
+    q = mlp.bf16_round(r)
+    assert np.all(np.abs(q - r) <= mlp.BF16_UNIT * np.abs(r) * (1 + 1e-6))
+    assert np.array_equal(mlp.bf16_round(q), q)
+
+
+def test_bf16_inference_bound_holds_for_an_emulation():
+    """Brute force: the network evaluated in numpy float32 with BF16 weights and every hidden
+    activation rounded to BF16 lies within the bound of bf16_inference, and the bound is not vacuous
+    (the largest emulated error is a visible share of it: rounding errors of a 64-term sum mostly
+    cancel, which the worst-case bound does not assume)."""
+    rng = np.random.default_rng(2)
+    th = mlp.init_params(rng) + 0.1 * rng.normal(size=mlp.N_PARAMS)
+    x = rng.uniform(-1, 1, size=(3000, 2))
+    y, ey = mlp.bf16_inference(th, x)
+    p = mlp.unpack(th)
+    W = {k: mlp.bf16_round(p[k]).astype(np.float32) for k in ("W1", "W2", "W3", "W4")}
+    h = x.astype(np.float32)
+    for k, b in (("W1", "b1"), ("W2", "b2"), ("W3", "b3")):
+        a = (h @ W[k].T + p[b].astype(np.float32)).astype(np.float32)
+        h = mlp.bf16_round(a / (np.float32(1) + np.exp(-a))).astype(np.float32)
+    ye = (h @ W["W4"].T + p["b4"].astype(np.float32)).astype(np.float64)
+    d = np.abs(ye - y)
+    assert np.all(d <= ey)
+    assert (d / ey).max() > 0.01
+    # the BF16 weights alone move the heads by far more than the bound's FP32 terms
+    y64, _ = mlp.forward(th, x)
+    assert np.abs(y64 - y).max() > 10 * mlp.FP32_UNIT * np.abs(y).max()
