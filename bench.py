@@ -33,6 +33,7 @@ METRIC = "ms per EXC eval (rho+E_xc+Vxc) & TFLOP/s, mixed vs FP64, at 1e-6 Eh er
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X dense MFMA peaks
 GOLDEN = os.path.join(ROOT, "tests", "golden", "cfg1_oracle.json")            # dense (unscreened)
 GOLDEN_BLOCKED = os.path.join(ROOT, "tests", "golden", "cfg1_blocked.json")   # the method at t = 1e-10
+GOLDEN_BLOCKED_OVERLAP = os.path.join(ROOT, "tests", "golden", "cfg1_overlap_blocked.json")  # same, clustered order
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -93,8 +94,51 @@ def cpu_baseline(p, n_sample=300000, seed=0):
     dt = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0))
     return {"value": dt * 1e3 * p.n_points / len(idx), "unit": "ms/eval", "cores": cores, "kind": "oracle",
+            "blas": blas_vendor(),
             "sample": "%d of %d grid points (seeded random subset), dense FP64 oracle, %.1f s measured, "
                       "scaled linearly to all points" % (len(idx), p.n_points, dt)}
+
+
+def blas_vendor():
+    """The BLAS library NumPy was built against (name and version), as NumPy reports it."""
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg["Build Dependencies"]["blas"]
+        return "%s %s" % (b.get("name", "?"), b.get("version", ""))
+    except Exception:   # older NumPy: no dict form
+        return "unknown"
+
+
+def sweep(p, D, steps, warmup, torch, Plan, gd, so=None):
+    """Thresholds t_b = t_d = t on the mixed path: retained fraction, executed pairs, ms/eval, and the
+    errors of E_xc and of sampled Vxc entries against the unscreened FP64 oracle (gd) and against the
+    FP64 GPU path at the same thresholds."""
+    ij = np.array(gd["v_ij"])
+    rows = []
+    for t in (1e-8, 1e-9, 1e-10, 1e-11, 1e-12, 1e-14, 0.0):
+        r = {"t": t}
+        for prec in ("fp32", "fp64"):
+            plan = Plan.from_problem(p, prec=prec, t_b=t, t_d=t, shell_order=so)
+            info = plan.info()
+            ms, stage, st, E, V, rho = time_path(plan, D, steps, warmup, torch)
+            dv = max(np.abs(V[ij[:, 0], ij[:, 1]] - np.array(gd["v"])).max(),
+                     np.abs(np.diag(V) - np.array(gd["v_diag"])).max())
+            r[prec] = {"ms": round(ms, 3), "E": E, "dE_vs_dense": abs(E - gd["E"]), "dV_vs_dense_sampled": dv,
+                       "V": V}
+            if prec == "fp32":
+                r.update(retained_fraction=info["retained_fraction"], n_pairs_x=st["n_pairs_x"],
+                         n_pairs_v=st["n_pairs_v"], chunks=info["n_grid_chunks"])
+            plan.close()
+            del rho
+            torch.cuda.empty_cache()
+            log("sweep t=%g %s: %.2f ms, retained %.4f, dE vs dense %.2e, dV %.2e" % (
+                t, prec, ms, info["retained_fraction"], abs(E - gd["E"]), dv))
+        r["fp32"]["dE_vs_fp64"] = abs(r["fp32"]["E"] - r["fp64"]["E"])
+        r["fp32"]["dV_vs_fp64"] = float(np.abs(r["fp32"]["V"] - r["fp64"]["V"]).max())
+        for prec in ("fp32", "fp64"):
+            del r[prec]["V"]
+        rows.append(r)
+    return rows
 
 
 def time_batch(B, D, steps, warmup, torch):
@@ -334,8 +378,12 @@ def main():
     ap.add_argument("--epochs", type=int, default=10, help="training epochs of the learned form (--config 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--ao-order", default="both", choices=["atom", "both"],
-                    help="both: also time the headline form with the overlap-signature basis order (workload 1)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="threshold sweep t_b = t_d on workload 1 (retained fraction, time, errors) instead of the bench")
+    ap.add_argument("--no-dense", action="store_true", help="skip the unscreened (t_b = t_d = 0) GPU comparator")
+    ap.add_argument("--ao-order", default="overlap", choices=["overlap", "atom"],
+                    help="basis order of the timed plans on workloads 1 and 2: overlap-signature clustering (the "
+                         "paper's reordering; default) or atom order; workload 1 also times the other order once")
     ap.add_argument("--precs", default="fp32,bf16x6,bf16x3",
                     help="precision forms timed beside FP64 (workloads 1 and 2); the first is the headline value")
     ap.add_argument("--v-segment", type=int, default=0, help="grid blocks per Vxc segment (0 = plan's choice)")
@@ -371,11 +419,26 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    so, order_ms = None, 0.0
+    if args.ao_order == "overlap":
+        from paper_2605_10363_amd.plan import overlap_order
+        S = synth.overlap_matrix(p.basis, p.atom_xyz)   # an input (the SCF setup has it), not timed
+        t0 = time.time()
+        _, so = overlap_order(p.basis, S)
+        order_ms = (time.time() - t0) * 1e3
+        del S
+        log("overlap-signature basis order: %.0f ms" % order_ms)
+    if args.sweep:
+        gd = json.load(open(GOLDEN))
+        rows = sweep(p, D, args.steps, args.warmup, torch, Plan, gd, so)
+        print(json.dumps({"workload": WORKLOADS.get(args.config), "sweep": rows}), flush=True)
+        return
     res = {}
     forms = [f for f in args.precs.split(",") if f]
     for prec in (forms if args.no_fp64 else forms + ["fp64"]):
+        torch.cuda.synchronize()
         t0 = time.time()
-        plan = Plan.from_problem(p, prec=prec, v_segment=args.v_segment,
+        plan = Plan.from_problem(p, prec=prec, v_segment=args.v_segment, shell_order=so,
                                  schedule="grid" if args.schedule == "auto" else args.schedule)
         tune = plan.autotune(D, reps=2) if args.schedule == "auto" else None
         info = plan.info()
@@ -384,10 +447,13 @@ def main():
         log("%s plan: %.0f ms, retained fraction %.4f, n_ret %d, max tiles/block %d, %d V items, %.1f GB" % (
             prec, info["plan_ms"], info["retained_fraction"], info["n_retained_tiles"], info["max_tiles_per_block"],
             info["n_v_items"], info["workspace_bytes"] / 1e9))
+        plan.eval(D)
+        torch.cuda.synchronize()
+        cold_ms = (time.time() - t0) * 1e3 + order_ms
         ms, stage, st, E, V, rho = time_path(plan, D, args.steps, args.warmup, torch)
         log("%s: %.3f ms/eval, stages %s, pairs x %d v %d, E %.12f" % (
             prec, ms, {k: round(v, 3) for k, v in stage.items()}, st["n_pairs_x"], st["n_pairs_v"], E))
-        res[prec] = dict(ms=ms, stage=stage, stats=st, E=E, V=V, info=info,
+        res[prec] = dict(ms=ms, stage=stage, stats=st, E=E, V=V, info=info, cold_ms=cold_ms,
                          elec=float(torch.dot(rho, torch.from_numpy(p.grid.weight).cuda()).item()))
         plan.close()
         del rho
@@ -401,11 +467,15 @@ def main():
         "vs_baseline": None, "dtype": DTYPE[forms[0]], "data": "synthetic",
         "config": {"workload": WORKLOADS.get(args.config, "config %d" % args.config),
                    "path": PATHS[forms[0]],
+                   "basis_order": "overlap-signature clustering" if so is not None else "atom order",
                    "seeds": p.meta.get("seeds")},
         "tflops": round(flops / (mix["ms"] * 1e-3) / 1e12, 3),
         "gemm_flops_per_eval": flops,
         "retained_fraction": mix["info"]["retained_fraction"],
         "stage_ms": {k: round(v, 4) for k, v in mix["stage"].items()},
+        "plan_ms": round(mix["info"]["plan_ms"] + order_ms, 1),
+        "basis_order_ms": round(order_ms, 1),
+        "cold_ms": round(mix["cold_ms"], 1),
         "electrons": mix["elec"], "n_occ": p.n_occ,
     }
     if "fp64" in res:
@@ -425,7 +495,7 @@ def main():
         out["precision_forms"][prec] = d
     if args.config == 1:
         out["err_vs_oracle"] = {}
-        for tag, path in (("blocked", GOLDEN_BLOCKED), ("dense", GOLDEN)):
+        for tag, path in (("blocked", GOLDEN_BLOCKED_OVERLAP if so is not None else GOLDEN_BLOCKED), ("dense", GOLDEN)):
             if not os.path.exists(path):
                 continue
             g = json.load(open(path))
@@ -436,27 +506,38 @@ def main():
                          np.abs(np.diag(V) - np.array(g["v_diag"])).max())
                 out["err_vs_oracle"]["%s_%s" % (tag, prec)] = {"E_xc": abs(r["E"] - g["E"]), "V_maxabs_sampled": dv}
 
-    if args.config == 1 and args.ao_order == "both":
-        from paper_2605_10363_amd.plan import overlap_order
-        S = synth.overlap_matrix(p.basis, p.atom_xyz)   # an input (the SCF setup has it), not timed
-        t0 = time.time()
-        _, so = overlap_order(p.basis, S)
-        order_ms = (time.time() - t0) * 1e3
-        plan = Plan.from_problem(p, prec=forms[0], v_segment=args.v_segment, shell_order=so)
+    if args.config == 1 and not args.no_dense:
+        plan = Plan.from_problem(p, prec=forms[0], t_b=0.0, t_d=0.0, shell_order=so)
+        info = plan.info()
+        ms, stage, st, E, V, rho = time_path(plan, D, max(3, args.steps // 2), 1, torch)
+        log("%s unscreened (t_b = t_d = 0): %.3f ms/eval, %d chunks, pairs x %d v %d" % (
+            forms[0], ms, info["n_grid_chunks"], st["n_pairs_x"], st["n_pairs_v"]))
+        out["dense"] = {"what": "the same kernels with every candidate tile retained and every pair executed "
+                                "(t_b = t_d = 0): the dense-GPU comparator", "ms": round(ms, 3),
+                        "speedup_block_filtered": round(ms / mix["ms"], 3), "n_pairs_x": st["n_pairs_x"],
+                        "n_pairs_v": st["n_pairs_v"], "grid_chunks": info["n_grid_chunks"],
+                        "tflops": round(st["gemm_flops"] / (ms * 1e-3) / 1e12, 3)}
+        plan.close()
+        del rho
+        torch.cuda.empty_cache()
+    if args.config == 1:
+        other = "atom order" if so is not None else "overlap-signature clustering"
+        so2 = None
+        if so is None:
+            from paper_2605_10363_amd.plan import overlap_order
+            _, so2 = overlap_order(p.basis, synth.overlap_matrix(p.basis, p.atom_xyz))
+        plan = Plan.from_problem(p, prec=forms[0], v_segment=args.v_segment, shell_order=so2)
         info = plan.info()
         ms, stage, st, E, V, rho = time_path(plan, D, args.steps, args.warmup, torch)
-        log("%s, overlap-clustered basis order: %.3f ms/eval, retained fraction %.4f, pairs x %d v %d (order %.0f ms)" % (
-            forms[0], ms, info["retained_fraction"], st["n_pairs_x"], st["n_pairs_v"], order_ms))
-        out["ao_order_overlap"] = {
-            "what": "the headline form with basis functions ordered by overlap-signature clustering (kldi_overlap_order) "
-                    "instead of atom order",
-            "order_ms": round(order_ms, 1), "ms": round(ms, 4), "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        log("%s, %s: %.3f ms/eval, retained fraction %.4f, pairs x %d v %d" % (
+            forms[0], other, ms, info["retained_fraction"], st["n_pairs_x"], st["n_pairs_v"]))
+        out["other_basis_order"] = {
+            "order": other, "ms": round(ms, 4), "stage_ms": {k: round(v, 4) for k, v in stage.items()},
             "retained_fraction": info["retained_fraction"], "n_retained_tiles": info["n_retained_tiles"],
-            "n_pairs_x": st["n_pairs_x"], "n_pairs_v": st["n_pairs_v"],
-            "atom_order": {"ms": round(mix["ms"], 4), "retained_fraction": mix["info"]["retained_fraction"],
-                           "n_retained_tiles": mix["info"]["n_retained_tiles"],
-                           "n_pairs_x": mix["stats"]["n_pairs_x"], "n_pairs_v": mix["stats"]["n_pairs_v"]},
-            "E_xc_diff_vs_atom_order": abs(E - mix["E"])}
+            "n_pairs_x": st["n_pairs_x"], "n_pairs_v": st["n_pairs_v"], "E_xc_diff": abs(E - mix["E"]),
+            "headline": {"ms": round(mix["ms"], 4), "retained_fraction": mix["info"]["retained_fraction"],
+                         "n_retained_tiles": mix["info"]["n_retained_tiles"], "n_pairs_x": mix["stats"]["n_pairs_x"],
+                         "n_pairs_v": mix["stats"]["n_pairs_v"]}}
         plan.close()
         del rho
         torch.cuda.empty_cache()

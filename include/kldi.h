@@ -61,7 +61,12 @@ typedef enum {
 typedef enum {
   KLDI_XC_LDA_X = 1,        /* Slater exchange f = -(3/4)(3/pi)^(1/3) rho^(4/3)                  */
   KLDI_XC_PBE = 2,          /* PBE exchange + PW92 correlation + PBE gradient correction          */
-  KLDI_XC_PBE_X = 3         /* PBE exchange only                                                   */
+  KLDI_XC_PBE_X = 3,        /* PBE exchange only                                                   */
+  /* Meta-GGA (the kinetic-energy density path of the paper's M06-2X, whose parameters are not
+   * available here): MVS exchange (Sun, Perdew, Ruzsinszky 2015), F_x(s, alpha), alpha = (tau - tau_W) /
+   * tau_unif, tau = 1/2 sum D grad chi . grad chi; FP64 plans only (KLDI_E_UNSUPPORTED otherwise). */
+  KLDI_XC_MVS = 4,          /* MVS exchange + PBE correlation                                      */
+  KLDI_XC_MVS_X = 5         /* MVS exchange only                                                   */
 } kldi_xc;
 
 /* Working precision of the block GEMMs.  The functional, rho accumulation across tiles, E_xc and
@@ -118,7 +123,11 @@ typedef struct {
   double t_b;                    /* block-retention threshold (eq. block_filter_A), >= 0          */
   double t_d;                    /* block-pair execution threshold (eq. block_pair_filter), >= 0  */
   double rho_cut;                /* points with rho <= rho_cut get f = v = 0, >= 0                 */
-  int32_t grid_block;            /* G, points per grid block; the library supports 128             */
+  int32_t grid_block;            /* G, points per screening block: 128 or 256.  Both screen and
+                                    filter per G-point block (S_Phi, a_pq, b_pr, z_qr at that
+                                    granularity); the kernels compute in 128-point blocks, the
+                                    two halves of a 256-point block sharing its retained tiles
+                                    and summaries                                                 */
   int32_t ao_block;              /* d, AOs per tile; the library supports 32                       */
   int32_t prec;                  /* kldi_prec                                                     */
   int32_t xc;                    /* kldi_xc                                                       */
@@ -183,7 +192,7 @@ void kldi_opts_default(kldi_opts *opts);
  * lists BCS(C) (Appendix C), the Vxc work list, and all device workspaces.
  * basis, grid, opts: host pointers (copied).  stream: hipStream_t or NULL.  *out receives the
  * plan, owned by the caller and released with kldi_plan_destroy.
- * Errors: KLDI_E_ARG (validation), KLDI_E_UNSUPPORTED (grid_block != 128, ao_block != 32, or more
+ * Errors: KLDI_E_ARG (validation), KLDI_E_UNSUPPORTED (grid_block not 128 or 256, ao_block != 32, or more
  * than 512 retained AO tiles, i.e. 16,384 AOs, in one grid block), KLDI_E_OOM, KLDI_E_HIP.  On error
  * *out is set to NULL and nothing is leaked.  A plan with no retained tile (thresholds above every block
  * maximum) is valid: its evaluations return exact zeros. */
@@ -368,6 +377,22 @@ kldi_status kldi_plan_timing(kldi_plan *plan, int32_t enable);
  * evaluations timed since kldi_plan_timing(plan, 1) to stage_ms[KLDI_N_STAGES] (host), and their
  * number to *n_evals (host, may be NULL).  Stages that did not run (no Vxc requested) read 0. */
 kldi_status kldi_eval_timing(kldi_plan *plan, double *stage_ms, int32_t *n_evals);
+
+/* Nuclear gradient of E_xc with the grid held fixed (the EXC gradient of Sec. IV-B, Fig. 5(b); the grid
+ * points and weights do not move with the atoms, a reading: the paper does not say).  The basis
+ * functions of atom A move with R_A, so
+ *   dE_xc/dR_Aa = -2 sum_{mu on A} sum_nu D_{mu nu} K^a_{mu nu},
+ *   K^a = (d_a Phi) W^T + Q^a Phi^T,  W = w v_rho Phi + sum_b c_b d_b Phi,  Q^a = sum_b c_b d_a d_b Phi,
+ * c_b = 2 w v_sigma d_b rho (zero for LDA), evaluated like the energy: Phi on retained tiles, rho and
+ * the functional as kldi_eval, and the products of the Vxc shape on the tile pairs (p, q) whose
+ * operands are retained at a grid block and whose D block is retained (a_pq >= t_b).
+ *   D_dev     as for kldi_eval (device, n_ao x n_ao, caller order)
+ *   grad_dev  [n_atoms * 3] device, caller atom order, (x, y, z) per atom, Eh/bohr
+ *   exc_dev   1 double on the device, or NULL: E_xc of the same evaluation
+ * Single-molecule plans with KLDI_PREC_FP64 and the analytic functional (else KLDI_E_UNSUPPORTED).
+ * Allocates its workspaces on the plan on first use (KLDI_E_OOM if they do not fit); only enqueues
+ * work on `stream`. */
+kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_dev, double *exc_dev, void *stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *kldi_last_error(void);

@@ -92,3 +92,65 @@ def eval_ao(atom_xyz, basis, pts, deriv=0):
                     dphi[ax, mu] = nr * (dang * R + ang * d[:, ax] * R1)
             mu += 1
     return (phi, dphi) if deriv else phi
+
+
+def eval_ao_hess(atom_xyz, basis, pts):
+    """Phi (n_ao x P), grad Phi (3 x n_ao x P) and the second derivatives d_a d_b Phi (3 x 3 x n_ao x P).
+
+    With A(d) = dx^lx dy^ly dz^lz and R(r^2) as above, R1 = sum_k (-2 a_k) c_k e^{-a_k r^2} and
+    R2 = sum_k (2 a_k)^2 c_k e^{-a_k r^2} (so d_a R = d_a R1, d_b (d_a R1) = delta_ab R1 + d_a d_b R2):
+        d_a d_b chi = N_rel [A_ab R + A_a d_b R1 + A_b d_a R1 + A (delta_ab R1 + d_a d_b R2)],
+    A_a, A_ab the first and second derivatives of the monomial."""
+    pts = np.asarray(pts, dtype=np.float64)
+    P = pts.shape[0]
+    nao = n_ao(basis)
+    phi = np.zeros((nao, P))
+    dphi = np.zeros((3, nao, P))
+    hphi = np.zeros((3, 3, nao, P))
+    mu = 0
+
+    def mono(d, pw):
+        return d[:, 0] ** pw[0] * d[:, 1] ** pw[1] * d[:, 2] ** pw[2]
+
+    def dmono(d, pw, ax):
+        if pw[ax] == 0:
+            return np.zeros(d.shape[0])
+        q = list(pw)
+        q[ax] -= 1
+        return pw[ax] * mono(d, q)
+
+    def d2mono(d, pw, a, b):
+        if pw[a] == 0:
+            return np.zeros(d.shape[0])
+        q = list(pw)
+        c = q[a]
+        q[a] -= 1
+        return c * dmono(d, q, b)
+
+    for s in range(len(basis.shell_l)):
+        l = int(basis.shell_l[s])
+        A0 = atom_xyz[int(basis.shell_atom[s])]
+        d = pts - A0[None, :]
+        r2 = np.einsum("pi,pi->p", d, d)
+        R = np.zeros(P)
+        R1 = np.zeros(P)
+        R2 = np.zeros(P)
+        for k in range(int(basis.prim_ptr[s]), int(basis.prim_ptr[s + 1])):
+            al = float(basis.prim_exp[k])
+            e = float(basis.prim_coef[k]) * np.exp(-al * r2)
+            R += e
+            R1 += -2.0 * al * e
+            R2 += 4.0 * al * al * e
+        for pw in CART[l]:
+            nr = n_rel(*pw)
+            A = mono(d, pw)
+            Ad = [dmono(d, pw, a) for a in range(3)]
+            phi[mu] = nr * A * R
+            for a in range(3):
+                dphi[a, mu] = nr * (Ad[a] * R + A * d[:, a] * R1)
+                for b in range(3):
+                    h = d2mono(d, pw, a, b) * R + Ad[a] * d[:, b] * R1 + Ad[b] * d[:, a] * R1
+                    h = h + A * ((R1 if a == b else 0.0) + d[:, a] * d[:, b] * R2)
+                    hphi[a, b, mu] = nr * h
+            mu += 1
+    return phi, dphi, hphi

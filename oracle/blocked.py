@@ -39,7 +39,7 @@ from . import reorder as _reorder
 
 
 def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_d=1e-10,
-                 d_ao=32, G=128, rho_cut=1e-14, shell_order=None):
+                 d_ao=32, G=128, rho_cut=1e-14, shell_order=None, count_unit=None):
     atom_xyz = np.asarray(atom_xyz, np.float64)
     pts = np.asarray(pts, np.float64)
     w = np.asarray(weights, np.float64)
@@ -55,6 +55,8 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
     T = _reorder.tiles(nao, d_ao)
     B = _reorder.tiles(npt, G)
     nT, nB = len(T), len(B)
+    # executed pairs are counted per grid block, or per count_unit points of it (rounded up)
+    wt = [1 if not count_unit else -(-(g1 - g0) // count_unit) for (g0, g1) in B]
 
     # block summaries and retention
     b = np.zeros((nT, nB))
@@ -79,7 +81,7 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
                 continue
             mask = np.array([S_D[p, q] and S_phi[q, r] and a[p, q] * b[q, r] >= t_d for q in range(nT)])
             n_exec, E = addressing.parallel_where(mask)
-            nP_X += n_exec
+            nP_X += n_exec * wt[r]
             acc = np.zeros((a1 - a0, g1 - g0))
             for q in E:
                 c0, c1 = T[q]
@@ -96,7 +98,25 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
     rho = np.einsum("mi,mi->i", phik, X)
     grad = 2.0 * np.einsum("ami,mi->ai", dphik, X)
     sigma = np.einsum("ai,ai->i", grad, grad)
-    f, vr, vs = _fx.evaluate(xc, rho, sigma if gga else None, rho_cut)
+    mgga = _fx.is_mgga(xc)
+    if mgga:
+        # tau = (1/2) sum_a sum_p d_a Phi_pr (D d_a Phi)_pr on retained output blocks; the products run
+        # over every retained operand tile q with a retained D block (reading: no t_d filter, whose
+        # summaries are those of Phi)
+        tau = np.zeros(npt)
+        for ax in range(3):
+            Xa = np.zeros((nao, npt))
+            for r, (g0, g1) in enumerate(B):
+                for p, (a0, a1) in enumerate(T):
+                    if not S_phi[p, r]:
+                        continue
+                    for q, (c0, c1) in enumerate(T):
+                        if S_D[p, q] and S_phi[q, r]:
+                            Xa[a0:a1, g0:g1] += Dp[a0:a1, c0:c1] @ dphi[ax][c0:c1, g0:g1]
+            tau += 0.5 * np.einsum("mi,mi->i", dphik[ax], Xa)
+        f, vr, vs, vt = _fx.evaluate_mgga(xc, rho, sigma, tau, rho_cut)
+    else:
+        f, vr, vs = _fx.evaluate(xc, rho, sigma if gga else None, rho_cut)
     E = math.fsum((wp * f).tolist())
 
     # Z and its block summaries
@@ -118,12 +138,22 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
             mask = np.array([S_phi[p, r] and S_phi[q, r] and z[q, r] >= t_b and b[p, r] * z[q, r] >= t_d
                              for r in range(nB)])
             n_exec, E_M = addressing.parallel_where(mask)
-            nP_M += n_exec
+            nP_M += sum(wt[r] for r in E_M)
             acc = np.zeros((a1 - a0, c1 - c0))
             for r in E_M:
                 g0, g1 = B[r]
                 acc += phik[a0:a1, g0:g1] @ Z[c0:c1, g0:g1].T
             M[a0:a1, c0:c1] = acc
+    if mgga:
+        # the tau term of Vxc, sum_a d_a Phi diag(w v_tau / 4) d_a Phi^T, over every pair of retained
+        # tiles of a block (reading: no t_d filter)
+        ct = 0.25 * wp * vt
+        for p, (a0, a1) in enumerate(T):
+            for q, (c0, c1) in enumerate(T):
+                for r, (g0, g1) in enumerate(B):
+                    if S_phi[p, r] and S_phi[q, r]:
+                        for ax in range(3):
+                            M[a0:a1, c0:c1] += dphi[ax][a0:a1, g0:g1] @ (ct[g0:g1][None, :] * dphi[ax][c0:c1, g0:g1]).T
     if gga:
         Vp = M + M.T
     else:
@@ -140,14 +170,17 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
     # back to caller order
     rho_c = np.empty(npt)
     rho_c[pt_perm] = rho
+    grad_c = np.empty((3, npt))
+    grad_c[:, pt_perm] = grad
     V = np.empty((nao, nao))
     V[np.ix_(ao_perm, ao_perm)] = Vp
-    return dict(rho=rho_c, E=E, V=V, S_phi=S_phi, S_D=S_D, b=b, s=s, a=a, z=z, nP_X=nP_X, nP_M=nP_M,
+    return dict(rho=rho_c, grad=grad_c, E=E, V=V, S_phi=S_phi, S_D=S_D, b=b, s=s, a=a, z=z, nP_X=nP_X, nP_M=nP_M,
                 ao_perm=ao_perm, pt_perm=pt_perm, n_tiles=nT, n_blocks=nB)
 
 
 def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_d=1e-10, d_ao=32, G=128,
-                        rho_cut=1e-14, blocks_per_chunk=32, v_entries=None, progress=None, shell_order=None):
+                        rho_cut=1e-14, blocks_per_chunk=32, v_entries=None, progress=None, shell_order=None,
+                        count_unit=None):
     """The same block-filtered evaluation as eval_blocked, one grid block at a time, for inputs whose
     dense Phi does not fit in memory.
 
@@ -217,7 +250,8 @@ def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e
             rows = np.concatenate([np.arange(*T[p]) for p in R])
             # executable pairs of X at r: (p, q) in S_D, q retained, a_pq b_qr >= t_d
             ex = S_D[np.ix_(R, R)] & (a[np.ix_(R, R)] * b[R][None, :] >= t_d)
-            nP_X += int(ex.sum())
+            wt = 1 if not count_unit else -(-(g1 - g0) // count_unit)
+            nP_X += int(ex.sum()) * wt
             tr = np.searchsorted(R, tile_of[rows])                # position of each row's tile in R
             Dm = np.where(ex[np.ix_(tr, tr)], Dp[np.ix_(rows, rows)], 0.0)
             phr = ph[rows]
@@ -237,7 +271,7 @@ def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e
             exm = (z[None, :] >= t_b) & (b[R][:, None] * z[None, :] >= t_d)
             if not gga:
                 exm &= R[:, None] <= R[None, :]
-            nP_M += int(exm.sum())
+            nP_M += int(exm.sum()) * wt
             if v_entries is None:
                 Mr = np.where(exm[np.ix_(tr, tr)], phr @ Z.T, 0.0)
                 M[np.ix_(rows, rows)] += Mr

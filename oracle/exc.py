@@ -14,6 +14,11 @@ Follows Sec. II-A and Appendix A literally, chunked over grid points only to bou
    (eq. fxc_matrix_form, eq. w_def); the GGA terms are the standard extension (reading), chosen so
    that V = dE_xc/dD exactly.
 
+Meta-GGA (xc "mvs", "mvs_x"): also tau_i = (1/2) sum_a sum_{mu nu} D_{mu nu} d_a chi_mu d_a chi_nu =
+(1/2) sum_a sum_mu d_a Phi_{mu i} (D d_a Phi)_{mu i}, the functional's v_tau, and the Vxc term
+(1/2) sum_i w_i v_tau,i grad chi_mu . grad chi_nu (= dE/dD through tau), added to M as
+sum_a d_a Phi diag(w v_tau / 4) d_a Phi^T so that V = M + M^T carries it.
+
 All outputs are in the caller's AO and grid order.
 """
 from __future__ import annotations
@@ -34,6 +39,9 @@ def eval_exc(atom_xyz, basis, pts, weights, D, xc, rho_cut=1e-14, chunk=4096, wa
     P = pts.shape[0]
     nao = D.shape[0]
     gga = _fx.is_gga(xc)
+    mgga = _fx.is_mgga(xc)
+    tau_all = np.zeros(P) if mgga else None
+    vt_all = np.zeros(P) if mgga else None
     rho = np.zeros(P)
     grad = np.zeros((3, P)) if gga else None
     sigma = np.zeros(P) if gga else None
@@ -55,7 +63,13 @@ def eval_exc(atom_xyz, basis, pts, weights, D, xc, rho_cut=1e-14, chunk=4096, wa
             grad[:, c0:c1] = g
             s = np.einsum("ai,ai->i", g, g)
             sigma[c0:c1] = s
-            f, vr, vs = _fx.evaluate(xc, r, s, rho_cut)
+            if mgga:
+                t = 0.5 * sum(np.einsum("mi,mi->i", dphi[a], D @ dphi[a]) for a in range(3))
+                tau_all[c0:c1] = t
+                f, vr, vs, vt = _fx.evaluate_mgga(xc, r, s, t, rho_cut)
+                vt_all[c0:c1] = vt
+            else:
+                f, vr, vs = _fx.evaluate(xc, r, s, rho_cut)
         else:
             f, vr, vs = _fx.evaluate(xc, r, None, rho_cut)
         fpt[c0:c1] = f
@@ -67,11 +81,18 @@ def eval_exc(atom_xyz, basis, pts, weights, D, xc, rho_cut=1e-14, chunk=4096, wa
                 gd = np.einsum("ai,ami->mi", g, dphi)
                 Z += 2.0 * (w[c0:c1] * vs)[None, :] * gd
             M += phi @ Z.T
+            if mgga:
+                ct = 0.25 * w[c0:c1] * vt
+                for a in range(3):
+                    M += dphi[a] @ (ct[None, :] * dphi[a]).T
     E = math.fsum((w * fpt).tolist())
     out = dict(rho=rho, E=E, f=fpt, vrho=vr_all, vsigma=vs_all)
     if gga:
         out["grad"] = grad
         out["sigma"] = sigma
+    if mgga:
+        out["tau"] = tau_all
+        out["vtau"] = vt_all
     if want_v:
         out["V"] = M + M.T
     return out

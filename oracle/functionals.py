@@ -23,6 +23,14 @@ PBE correlation gradient correction (phi = 1):
     H = gamma ln(1 + (beta/gamma) t^2 (1 + A t^2) / (1 + A t^2 + A^2 t^4)),
     f_c = rho (eps_c + H).
 
+Meta-GGA (the tau path the paper's M06-2X needs; its parameters are not available, so a published
+meta-GGA exchange of simple form stands in): MVS exchange (Sun, Perdew, Ruzsinszky, PNAS 112, 685 (2015))
+with PBE correlation, tau = (1/2) sum_i |grad psi_i|^2 = (1/2) sum D_{mu nu} grad chi_mu . grad chi_nu,
+    alpha = (tau - tau_W) / tau_unif,  tau_W = sigma / (8 rho),  tau_unif = (3/10)(3 pi^2)^{2/3} rho^{5/3},
+    F_x = (1 + k0 f(alpha)) / (1 + b s^4)^{1/8},  f(alpha) = (1 - alpha) / ((1 + e1 alpha^2)^2 + c1 alpha^4)^{1/4},
+    k0 = 0.174, e1 = -1.6665, c1 = 0.7672, b = 0.0233,   f_x = -C_x rho^{4/3} F_x,
+returning also v_tau = df/dtau.
+
 Points with rho <= rho_cut get f = v_rho = v_sigma = 0 (reading: the paper gives no density floor).
 """
 from __future__ import annotations
@@ -108,6 +116,66 @@ def pbe_c(rho, sigma):
     return f, vrho, vsigma
 
 
+MVS_K0, MVS_E1, MVS_C1, MVS_B = 0.174, -1.6665, 0.7672, 0.0233
+CTAU = 0.3 * (3.0 * math.pi ** 2) ** (2.0 / 3.0)
+
+
+def mvs_x(rho, sigma, tau):
+    """MVS exchange: f, v_rho, v_sigma, v_tau."""
+    rho = np.asarray(rho, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    tau = np.asarray(tau, dtype=np.float64)
+    r13 = np.cbrt(rho)
+    kf = np.cbrt(3.0 * math.pi ** 2 * rho)
+    ds2_dsigma = 1.0 / (4.0 * kf * kf * rho * rho)
+    s2 = sigma * ds2_dsigma
+    tu = CTAU * rho * r13 * r13                      # tau_unif
+    tw = sigma / (8.0 * rho)                         # tau_W
+    alpha = (tau - tw) / tu
+    g = (1.0 + MVS_E1 * alpha ** 2) ** 2 + MVS_C1 * alpha ** 4
+    dg = 4.0 * MVS_E1 * alpha * (1.0 + MVS_E1 * alpha ** 2) + 4.0 * MVS_C1 * alpha ** 3
+    fa = (1.0 - alpha) * g ** -0.25
+    dfa = -g ** -0.25 - 0.25 * (1.0 - alpha) * g ** -1.25 * dg
+    den = (1.0 + MVS_B * s2 * s2) ** 0.125
+    F = (1.0 + MVS_K0 * fa) / den
+    dF_ds2 = -(1.0 + MVS_K0 * fa) * 0.125 * (1.0 + MVS_B * s2 * s2) ** -1.125 * 2.0 * MVS_B * s2
+    dF_da = MVS_K0 * dfa / den
+    e_lda = -CX * rho * r13
+    # d alpha / d rho, d sigma, d tau (tau_unif ~ rho^{5/3}, tau_W ~ sigma / rho)
+    da_drho = (sigma / (8.0 * rho * rho)) / tu - (5.0 / 3.0) * alpha / rho
+    da_dsigma = -1.0 / (8.0 * rho * tu)
+    da_dtau = 1.0 / tu
+    f = e_lda * F
+    vrho = -(4.0 / 3.0) * CX * r13 * F + e_lda * (dF_ds2 * (-8.0 / 3.0) * s2 / rho + dF_da * da_drho)
+    vsigma = e_lda * (dF_ds2 * ds2_dsigma + dF_da * da_dsigma)
+    vtau = e_lda * dF_da * da_dtau
+    return f, vrho, vsigma, vtau
+
+
+def evaluate_mgga(xc, rho, sigma, tau, rho_cut=1e-14):
+    """(f, v_rho, v_sigma, v_tau) for xc = "mvs" (MVS exchange + PBE correlation) or "mvs_x"; zero wherever
+    rho <= rho_cut."""
+    rho = np.asarray(rho, dtype=np.float64)
+    n = rho.shape[0]
+    out = [np.zeros(n) for _ in range(4)]
+    m = rho > rho_cut
+    if not np.any(m):
+        return tuple(out)
+    r, s, t = rho[m], np.asarray(sigma, np.float64)[m], np.asarray(tau, np.float64)[m]
+    fx, vrx, vsx, vtx = mvs_x(r, s, t)
+    if xc == "mvs":
+        fc, vrc, vsc = pbe_c(r, s)
+        fx, vrx, vsx = fx + fc, vrx + vrc, vsx + vsc
+    elif xc != "mvs_x":
+        raise ValueError(xc)
+    out[0][m], out[1][m], out[2][m], out[3][m] = fx, vrx, vsx, vtx
+    return tuple(out)
+
+
+def is_mgga(xc) -> bool:
+    return xc in ("mvs", "mvs_x")
+
+
 def evaluate(xc, rho, sigma=None, rho_cut=1e-14):
     """(f, v_rho, v_sigma) for xc in {"lda", "pbe", "pbe_x"}; zero wherever rho <= rho_cut."""
     rho = np.asarray(rho, dtype=np.float64)
@@ -135,4 +203,4 @@ def evaluate(xc, rho, sigma=None, rho_cut=1e-14):
 
 
 def is_gga(xc) -> bool:
-    return xc in ("pbe", "pbe_x")
+    return xc in ("pbe", "pbe_x", "mvs", "mvs_x")

@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 KLDI_OK = 0
 STATUS = {0: "KLDI_OK", -1: "KLDI_E_ARG", -2: "KLDI_E_OOM", -3: "KLDI_E_HIP", -4: "KLDI_E_UNSUPPORTED",
           -5: "KLDI_E_STATE", -6: "KLDI_E_NONFINITE"}
-XC = {"lda": 1, "pbe": 2, "pbe_x": 3}
+XC = {"lda": 1, "pbe": 2, "pbe_x": 3, "mvs": 4, "mvs_x": 5}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 3, "bf16x6": 4}
 SCHED = {"grid": 0, "queue": 1}
 
@@ -125,6 +125,8 @@ kldi_mlp_loss_grad = _sig("kldi_mlp_loss_grad", ctypes.c_int,
 kldi_mlp_step = _sig("kldi_mlp_step", ctypes.c_int,
                      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                       ctypes.c_void_p, ctypes.c_void_p])
+kldi_eval_grad = _sig("kldi_eval_grad", ctypes.c_int,
+                      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
 kldi_overlap_order = _sig("kldi_overlap_order", ctypes.c_int,
                           [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
 kldi_mlp_params = _sig("kldi_mlp_params", ctypes.c_int,
@@ -138,7 +140,7 @@ EXPORTS = sorted(["kldi_opts_default", "kldi_plan_create", "kldi_batch_create", 
                   "kldi_plan_graph", "kldi_plan_autotune", "kldi_plan_destroy", "kldi_plan_info",
                   "kldi_plan_structure", "kldi_eval", "kldi_eval_check", "kldi_plan_timing", "kldi_eval_timing",
                   "kldi_eval_grid", "kldi_xc_eval", "kldi_mlp_create", "kldi_mlp_destroy", "kldi_mlp_train",
-                  "kldi_mlp_forward", "kldi_mlp_loss_grad", "kldi_mlp_step", "kldi_mlp_params", "kldi_overlap_order", "kldi_plan_attach_mlp",
+                  "kldi_mlp_forward", "kldi_mlp_loss_grad", "kldi_mlp_step", "kldi_mlp_params", "kldi_overlap_order", "kldi_eval_grad", "kldi_plan_attach_mlp",
                   "kldi_last_error", "kldi_version"])
 STAGES = ["dprep", "basis", "xgemm", "xfunc", "vgemm", "vfinal"]
 

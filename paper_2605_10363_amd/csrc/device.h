@@ -172,6 +172,60 @@ __device__ __forceinline__ void eval_ao(const BasisDev &B, int ao, double x, dou
   gz = nr * ((lz ? lz * px[lx] * py[ly] * pz[lz - 1] : 0.0) * R + ang * dz * R1);
 }
 
+// Value, gradient and second derivatives h = (xx, xy, xz, yy, yz, zz) of one internal AO at (x, y, z);
+// zero on padding rows.  With A the monomial (N_rel included), R = sum c e^{-a r^2}, R1 = sum (-2a) c
+// e^{-a r^2}, R2 = sum (2a)^2 c e^{-a r^2}:  d_a chi = A_a R + A d_a R1,
+// d_a d_b chi = A_ab R + A_a d_b R1 + A_b d_a R1 + A (delta_ab R1 + d_a d_b R2).
+__device__ __forceinline__ void eval_ao_hess(const BasisDev &B, int ao, double x, double y, double z, double &v,
+                                             double *g, double *h) {
+  v = 0.0;
+  for (int k = 0; k < 3; ++k) g[k] = 0.0;
+  for (int k = 0; k < 6; ++k) h[k] = 0.0;
+  const int s = B.ao_shell[ao];
+  if (s < 0) return;
+  const double d[3] = {x - B.sh_xyz[3 * s], y - B.sh_xyz[3 * s + 1], z - B.sh_xyz[3 * s + 2]};
+  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double R = 0.0, R1 = 0.0, R2 = 0.0;
+  for (int k = B.sh_prim[2 * s]; k < B.sh_prim[2 * s + 1]; ++k) {
+    const double a2 = 2.0 * B.pexp[k];
+    const double e = B.pcoef[k] * exp(-B.pexp[k] * r2);
+    R += e;
+    R1 -= a2 * e;
+    R2 += a2 * a2 * e;
+  }
+  const int cp = B.ao_comp[ao];
+  const int l[3] = {cp & 3, (cp >> 2) & 3, (cp >> 4) & 3};
+  const double nr = ((l[0] == 1) + (l[1] == 1) + (l[2] == 1) == 2) ? kSqrt3 : 1.0;
+  // t^l and its first two derivatives per axis
+  double p0[3], p1[3], p2[3];
+  for (int a = 0; a < 3; ++a) {
+    const double t = d[a];
+    p0[a] = l[a] == 0 ? 1.0 : (l[a] == 1 ? t : t * t);
+    p1[a] = l[a] == 0 ? 0.0 : (l[a] == 1 ? 1.0 : 2.0 * t);
+    p2[a] = l[a] == 2 ? 2.0 : 0.0;
+  }
+  const double A = nr * p0[0] * p0[1] * p0[2];
+  double Aa[3];
+  Aa[0] = nr * p1[0] * p0[1] * p0[2];
+  Aa[1] = nr * p0[0] * p1[1] * p0[2];
+  Aa[2] = nr * p0[0] * p0[1] * p1[2];
+  v = A * R;
+  for (int a = 0; a < 3; ++a) g[a] = Aa[a] * R + A * d[a] * R1;
+  int k = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = a; b < 3; ++b, ++k) {
+      double Aab;
+      if (a == b)
+        Aab = nr * (a == 0 ? p2[0] * p0[1] * p0[2] : (a == 1 ? p0[0] * p2[1] * p0[2] : p0[0] * p0[1] * p2[2]));
+      else {
+        const double q[3] = {(a == 0 || b == 0) ? p1[0] : p0[0], (a == 1 || b == 1) ? p1[1] : p0[1],
+                             (a == 2 || b == 2) ? p1[2] : p0[2]};
+        Aab = nr * q[0] * q[1] * q[2];
+      }
+      h[k] = Aab * R + Aa[a] * d[b] * R1 + Aa[b] * d[a] * R1 + A * ((a == b ? R1 : 0.0) + d[a] * d[b] * R2);
+    }
+}
+
 // ------------------------------------------------------------------------------------------------
 // Functionals, FP64 (spin-unpolarised).  LDA: Slater exchange.  PBE: PBE exchange (kappa = 0.804,
 // mu = beta pi^2/3), PW92 correlation (unpolarised fit), PBE gradient correction H (phi = 1).
@@ -241,6 +295,51 @@ __device__ __forceinline__ Xc xc_eval(int xc, double rho, double sigma, double r
   return Xc{x.f + c.f, x.vr + c.vr, x.vs + c.vs};
 }
 
+// Meta-GGA: MVS exchange (Sun, Perdew, Ruzsinszky 2015) with PBE correlation.  alpha = (tau - tau_W) /
+// tau_unif, tau_W = sigma / (8 rho), tau_unif = (3/10)(3 pi^2)^(2/3) rho^(5/3);
+// F_x = (1 + k0 f(alpha)) / (1 + b s^4)^(1/8), f = (1 - alpha) ((1 + e1 alpha^2)^2 + c1 alpha^4)^(-1/4).
+struct Xc4 {
+  double f, vr, vs, vt;
+};
+
+__device__ __forceinline__ Xc4 xc_mvs_x(double rho, double sigma, double tau) {
+  const double cx = 0.73855876638202234, k0 = 0.174, e1 = -1.6665, c1 = 0.7672, b = 0.0233;
+  const double ctau = 2.8712340001881915;   // (3/10)(3 pi^2)^(2/3)
+  const double r13 = cbrt(rho);
+  const double kf = cbrt(29.608813203268074 * rho);
+  const double ds2 = 1.0 / (4.0 * kf * kf * rho * rho);
+  const double s2 = sigma * ds2;
+  const double tu = ctau * rho * r13 * r13;
+  const double alpha = (tau - sigma / (8.0 * rho)) / tu;
+  const double a2 = alpha * alpha;
+  const double g = (1.0 + e1 * a2) * (1.0 + e1 * a2) + c1 * a2 * a2;
+  const double dg = 4.0 * e1 * alpha * (1.0 + e1 * a2) + 4.0 * c1 * a2 * alpha;
+  const double gq = pow(g, -0.25);
+  const double fa = (1.0 - alpha) * gq;
+  const double dfa = -gq - 0.25 * (1.0 - alpha) * gq / g * dg;
+  const double q = 1.0 + b * s2 * s2;
+  const double den = pow(q, 0.125);
+  const double num = 1.0 + k0 * fa;
+  const double F = num / den;
+  const double dF_ds2 = -num * 0.25 * b * s2 / (den * q);
+  const double dF_da = k0 * dfa / den;
+  const double el = -cx * rho * r13;
+  const double da_drho = (sigma / (8.0 * rho * rho)) / tu - (5.0 / 3.0) * alpha / rho;
+  const double da_dsigma = -1.0 / (8.0 * rho * tu);
+  return Xc4{el * F, -(4.0 / 3.0) * cx * r13 * F + el * (dF_ds2 * (-8.0 / 3.0) * s2 / rho + dF_da * da_drho),
+             el * (dF_ds2 * ds2 + dF_da * da_dsigma), el * dF_da / tu};
+}
+
+__device__ __forceinline__ Xc4 xc_eval_mgga(int xc, double rho, double sigma, double tau, double rho_cut) {
+  if (!(rho > rho_cut)) return Xc4{0.0, 0.0, 0.0, 0.0};
+  Xc4 x = xc_mvs_x(rho, sigma, tau);
+  if (xc == KLDI_XC_MVS_X) return x;
+  const Xc c = xc_pbe_c(rho, sigma);
+  return Xc4{x.f + c.f, x.vr + c.vr, x.vs + c.vs, x.vt};
+}
+
+__device__ __forceinline__ bool is_mgga(int xc) { return xc == KLDI_XC_MVS || xc == KLDI_XC_MVS_X; }
+
 struct FArgs {
   GridDev g;
   const int64_t *blk_item_off;   // [n_blocks+1] X work items of each block
@@ -253,6 +352,9 @@ struct FArgs {
   double rho_cut;
   int xc;
   int gga;
+  const double *tpart[3];        // meta-GGA: the X-type partials of D d_a Phi (component 1 + a holds
+                                 // 2 sum_mu d_a chi_mu (D d_a Phi)_mu), else NULL
+  double *ctau;                  // meta-GGA: [n_pad] w v_tau / 4 per point
 };
 
 }  // namespace dev

@@ -172,12 +172,15 @@ void validate_opts(const kldi_opts *o) {
       !std::isfinite(o->t_d) || !std::isfinite(o->rho_cut))
     fail(KLDI_E_ARG, "t_b, t_d and rho_cut must be finite and >= 0");
   if (o->grid_block <= 0 || o->grid_block % 64 != 0) fail(KLDI_E_ARG, "grid_block must be a positive multiple of 64");
-  if (o->grid_block != kG) fail(KLDI_E_UNSUPPORTED, "libkldi supports grid_block = 128");
+  if (o->grid_block != kG && o->grid_block != 2 * kG) fail(KLDI_E_UNSUPPORTED, "libkldi supports grid_block = 128 or 256");
   if (o->ao_block != kD) fail(KLDI_E_UNSUPPORTED, "libkldi supports ao_block = 32");
   if (o->prec != KLDI_PREC_FP64 && o->prec != KLDI_PREC_FP32 && o->prec != KLDI_PREC_BF16X3 &&
       o->prec != KLDI_PREC_BF16X6)
     fail(KLDI_E_ARG, "unknown prec");
-  if (o->xc != KLDI_XC_LDA_X && o->xc != KLDI_XC_PBE && o->xc != KLDI_XC_PBE_X) fail(KLDI_E_ARG, "unknown xc");
+  if (o->xc != KLDI_XC_LDA_X && o->xc != KLDI_XC_PBE && o->xc != KLDI_XC_PBE_X && !is_mgga_xc(o->xc))
+    fail(KLDI_E_ARG, "unknown xc");
+  if (is_mgga_xc(o->xc) && o->prec != KLDI_PREC_FP64)
+    fail(KLDI_E_UNSUPPORTED, "the meta-GGA functionals run on FP64 plans");
   if (o->v_segment < 0) fail(KLDI_E_ARG, "v_segment must be >= 0");
   if (o->chunk_tiles < 0) fail(KLDI_E_ARG, "chunk_tiles must be >= 0");
   if (o->schedule != KLDI_SCHED_GRID && o->schedule != KLDI_SCHED_QUEUE) fail(KLDI_E_ARG, "unknown schedule");
@@ -220,13 +223,15 @@ struct MolPrep {
   std::vector<int64_t> pt_perm;        // internal -> caller point
   std::vector<double> sh_xyz, pexp, pcoef;
   std::vector<int> sh_prim, sh_l, sh_ao0, ao_shell, ao_comp, tile_sh, tile_nv;
+  std::vector<int> ao_atom;            // internal AO -> caller atom (-1 on padding)
   std::vector<double> px, py, pz, pw;
   std::vector<int64_t> porig;
   std::vector<int> cand_p;
   std::vector<int64_t> cand_r;
 };
 
-void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, double t_b, const int32_t *shell_seq) {
+void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, double t_b, const int32_t *shell_seq,
+                 int pair_blocks) {
   const int na = b->n_atoms, ns = b->n_shells;
   const int64_t npt = g->n_points;
   M.n_points = npt;
@@ -287,6 +292,7 @@ void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, 
   M.ao_shell.assign(nao_pad, -1);
   M.ao_comp.assign(nao_pad, 0);
   M.ao_perm.assign(M.n_ao, 0);
+  M.ao_atom.assign(nao_pad, -1);
   {
     int ao = 0;
     for (int is = 0; is < ns; ++is) {
@@ -307,6 +313,7 @@ void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, 
         M.ao_shell[ao] = is;
         M.ao_comp[ao] = lx | (ly << 2) | (lz << 4);
         M.ao_perm[ao] = int32_t(cao0[s] + c);
+        M.ao_atom[ao] = b->shell_atom[s];
         ++ao;
       }
     }
@@ -356,9 +363,12 @@ void prepare_mol(MolPrep &M, const kldi_basis *b, const kldi_grid *g, bool gga, 
   for (int is = 0; is < ns; ++is)
     rad[is] = shell_radius(M.sh_l[is], &M.pexp[M.sh_prim[2 * is]], &M.pcoef[M.sh_prim[2 * is]],
                            M.sh_prim[2 * is + 1] - M.sh_prim[2 * is], gga, t_b);
+  // 256-point screening blocks (pair_blocks): the two 128-point compute blocks of a pair share the
+  // bounding box, hence the candidate list
   for (int64_t r = 0; r < M.n_blocks; ++r) {
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int64_t i = r * kG; i < std::min(npt, (r + 1) * kG); ++i) {
+    const int64_t rb0 = pair_blocks ? (r & ~int64_t(1)) : r, rb1 = pair_blocks ? rb0 + 2 : r + 1;
+    for (int64_t i = rb0 * kG; i < std::min(npt, rb1 * kG); ++i) {
       lo[0] = std::min(lo[0], M.px[i]); hi[0] = std::max(hi[0], M.px[i]);
       lo[1] = std::min(lo[1], M.py[i]); hi[1] = std::max(hi[1], M.py[i]);
       lo[2] = std::min(lo[2], M.pz[i]); hi[2] = std::max(hi[2], M.pz[i]);
@@ -491,6 +501,7 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
                                  " grid blocks");
   free_list(P.sched_allocs);
   P.sched_bytes = 0;
+  P.grad_ws = Plan::GradWs{};
   P.items_h.clear();
   P.chunks_h.clear();
   P.blk_item_off_h.clear();
@@ -525,6 +536,9 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
     for (seg = 16;; seg *= 2)
       if (size_t(count_v_items(P, blk_chunks, seg)) * 16384 * 8 <= budget || seg >= maxblk) break;
   }
+  // 256-point blocks pair compute blocks 2k, 2k + 1 of a molecule: segments (and so grid chunks) start at
+  // even offsets
+  if (P.opts.grid_block == 2 * kG && (seg & 1)) ++seg;
   P.v_segment = seg;
   P.schedule = schedule;
   std::vector<std::vector<int>> pair_lists(P.n_pairs);
@@ -580,7 +594,8 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
   // grid chunks: whole segments whose retained tiles fit the Phi / Z workspaces
   const size_t esz = (P.opts.prec == KLDI_PREC_FP64) ? 8 : 4;
   // Phi + Z (+ bf16 low part of Phi) (+ the BF16 pieces of Phi for the X product)
-  const size_t per_tile = 2 * 4096 * esz + (esz == 4 ? 4096 * 2 : 0) + size_t(4096) * 2 * bf16_pieces(P.opts.prec);
+  const size_t per_tile = 2 * 4096 * esz + (esz == 4 ? 4096 * 2 : 0) + size_t(4096) * 2 * bf16_pieces(P.opts.prec) +
+                          (is_mgga_xc(P.opts.xc) ? size_t(2) * 4096 * 8 : 0);
   const size_t vfixed = P.items_h.size() * (16384 * 8 + 4);
   int64_t cap = chunk_tiles;
   {
@@ -611,6 +626,7 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
     max_xit = std::max(max_xit, C.xit1 - C.xit0);
     max_vm = std::max(max_vm, P.vmoff_h[C.blk1] - P.vmoff_h[C.blk0]);
   }
+  P.max_ret = max_ret;
 
   // per-XCD item orders of the schedule, per grid chunk
   const size_t nch = P.chunks_h.size();
@@ -695,6 +711,14 @@ void build_schedule(Plan &P, int seg, int schedule, int64_t chunk_tiles) {
   const int npc = bf16_pieces(P.opts.prec);
   E.phix = npc ? dev_alloc<unsigned short>(P, size_t(max_ret) * 4096 * npc, true) : nullptr;
   E.xpart = dev_alloc<double>(P, size_t(max_xit) * 4 * kG, true);
+  if (is_mgga_xc(P.opts.xc)) {
+    E.tdphi = dev_alloc<double>(P, size_t(max_ret) * 4096, true);
+    E.tB = dev_alloc<double>(P, size_t(max_ret) * 4096, true);
+    for (int a = 0; a < 3; ++a) E.tpart[a] = dev_alloc<double>(P, size_t(max_xit) * 4 * kG, true);
+  } else {
+    E.tdphi = E.tB = nullptr;
+    E.tpart[0] = E.tpart[1] = E.tpart[2] = nullptr;
+  }
   E.vpart = dev_alloc<double>(P, P.items_h.size() * 16384, true);
   E.vflag = dev_alloc<int>(P, P.items_h.size(), true);
   E.vmask = dev_alloc<unsigned short>(P, size_t(max_vm), true);
@@ -721,7 +745,7 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
     auto work = [&] {
       for (int m = next++; m < n_mol; m = next++) {
         try {
-          prepare_mol(mp[m], &bs[m], &gs[m], P.gga, o->t_b, o->shell_order);
+          prepare_mol(mp[m], &bs[m], &gs[m], P.gga, o->t_b, o->shell_order, o->grid_block == 2 * kG);
         } catch (const Error &e) {
           codes[m] = e.code;
           errs[m] = e.msg;
@@ -823,6 +847,7 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
       ptoff += M.n_points;
     }
   }
+  std::vector<int> ao_atom0 = mp[0].ao_atom;   // kept for the gradient (first molecule)
   mp.clear();
   mp.shrink_to_fit();
   P.n_cand = int64_t(cand_p.size());
@@ -867,6 +892,23 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
         P.allocs.erase(it);
       }
     }
+  }
+  if (o->grid_block == 2 * kG && P.n_cand > 0) {
+    // 256-point blocks: the summaries of a tile over a pair of compute blocks (molecule-local 2k, 2k + 1)
+    // are the maxima over both, so both halves retain the same tiles with the same b_pr
+    std::vector<int64_t> coff(P.n_blocks + 1, 0);
+    for (int64_t c = 0; c < P.n_cand; ++c) coff[cand_r[c] + 1]++;
+    for (int64_t r = 0; r < P.n_blocks; ++r) coff[r + 1] += coff[r];
+    for (const MolDev &mo : P.mols_h)
+      for (int64_t r = mo.blk0; r + 1 < mo.blk1; r += 2) {
+        const int64_t n = coff[r + 1] - coff[r];
+        if (coff[r + 2] - coff[r + 1] != n) fail(KLDI_E_ARG, "internal: paired blocks with different candidates");
+        for (int64_t k = 0; k < n; ++k) {
+          const int64_t c0 = coff[r] + k, c1 = coff[r + 1] + k;
+          cb[c0] = cb[c1] = std::max(cb[c0], cb[c1]);
+          cg[c0] = cg[c1] = std::max(cg[c0], cg[c1]);
+        }
+      }
   }
   P.blk_off_h.assign(P.n_blocks + 1, 0);
   std::vector<int> ret_r;
@@ -932,6 +974,8 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
     P.pair_info = dev_upload(P, pinfo);
   }
   P.ao_perm_d = dev_upload(P, P.ao_perm);
+  P.ao_atom = dev_upload(P, ao_atom0);
+  P.n_atoms0 = bs[0].n_atoms;
 
   // fixed workspaces
   const size_t esz = (o->prec == KLDI_PREC_FP64) ? 8 : 4;
@@ -948,7 +992,8 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
   E.coef = dev_alloc<double>(P, size_t(P.n_pad) * 4);
   E.eblk = dev_alloc<double>(P, P.n_blocks);
   E.mfull = dev_alloc<double>(P, size_t(P.n_mfull));
-  E.counters = dev_alloc<unsigned long long>(P, 4);
+  E.counters = dev_alloc<unsigned long long>(P, 8);
+  E.ctau = is_mgga_xc(o->xc) ? dev_alloc<double>(P, size_t(P.n_pad)) : nullptr;
   E.escratch = dev_alloc<double>(P, n_mol);
   E.io = dev_alloc<IoDev>(P, 1);
   check_hip(hipMemsetAsync(E.counters, 0, 4 * sizeof(unsigned long long), stream), "memset");
@@ -1189,6 +1234,30 @@ kldi_status kldi_eval(kldi_plan *plan, const double *D_dev, double *rho_dev, dou
     kldi::check_hip(hipSetDevice(P.device), "hipSetDevice");
     kldi::IoDev io{D_dev, rho_dev, nullptr, exc_dev, vxc_dev};
     kldi::run_eval(P, io, vxc_dev != nullptr, static_cast<hipStream_t>(stream), kldi::timing_slot(P));
+  });
+}
+
+kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_dev, double *exc_dev, void *stream) {
+  if (!plan || !D_dev || !grad_dev) {
+    kldi::set_error("plan, D and grad must not be NULL");
+    return KLDI_E_ARG;
+  }
+  return kldi::guarded([&] {
+    Plan &P = plan->impl;
+    if (P.n_mol != 1) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient is for single-molecule plans");
+    if (P.opts.prec != KLDI_PREC_FP64) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient runs on FP64 plans");
+    if (P.has_mlp) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient needs the analytic functional");
+    if (kldi::is_mgga_xc(P.opts.xc)) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient covers LDA and GGA functionals");
+    kldi::check_hip(hipSetDevice(P.device), "hipSetDevice");
+    if (!P.grad_ws.gA) {
+      P.grad_ws.gA = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.max_ret, 1)) * 4096, true);
+      P.grad_ws.gitem = kldi::dev_alloc<double>(P, std::max<size_t>(P.items_h.size(), 1) * 6 * 128, true);
+      P.grad_ws.gao = kldi::dev_alloc<double>(P, size_t(3) * P.mols_h[0].nc * 128, true);
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    kldi::IoDev io{D_dev, nullptr, nullptr, exc_dev ? exc_dev : P.ev.escratch, nullptr};
+    kldi::check_hip(kldi::launch_begin(P, io, s), "begin launch");
+    kldi::check_hip(kldi::launch_grad(P, grad_dev, s), "gradient launch");
   });
 }
 

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kG) void k_screen(BasisDev B, GridDev g, const int 
 // ------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void k_begin(IoDev *cell, IoDev io, unsigned long long *counters) {
   if (threadIdx.x == 0) *cell = io;
-  if (threadIdx.x < 4) counters[threadIdx.x] = 0ull;
+  if (threadIdx.x < 8) counters[threadIdx.x] = 0ull;
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -165,7 +165,8 @@ __global__ __launch_bounds__(NT) void k_dprep_b(const MolDev *__restrict__ mol, 
 
 // FP32 operands also get Phi_lo = bf16(Phi - fl32(Phi)) (phil != NULL): the term the split product of
 // the Vxc GEMM adds back.  BF16 split plans also get the NPC BF16 pieces of Phi in phix, per tile
-// [piece][point][AO] (the X product contracts over AOs).
+// [piece][unit u][point][8 AOs] (AOs 8u .. 8u + 7 of a point in one 16-byte unit: the X product contracts
+// over AOs, and consecutive threads store consecutive units).
 template <class T, int NPC>
 __global__ __launch_bounds__(kG) void k_basis(BasisDev B, GridDev g, StructDev st, int64_t ret0, T *__restrict__ phi,
                                              unsigned short *__restrict__ phil, unsigned short *__restrict__ phix) {
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(kG) void k_basis(BasisDev B, GridDev g, StructDev s
     // this point's row of each piece, 16 bytes (8 AOs) at a time: the AOs of a tile arrive in
     // increasing order (the same order in every thread), so a unit is stored once its last AO is in;
     // units past the tile's AOs are zero
-    unsigned short *px = phix + size_t(blockIdx.x) * (NPC * kG * kD) + size_t(j) * kD;
+    unsigned short *px = phix + size_t(blockIdx.x) * (NPC * kG * kD) + size_t(j) * 8;
     uint32_t bw[NPC][4];
     int cu = 0;
     auto clear = [&]() {
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(kG) void k_basis(BasisDev B, GridDev g, StructDev s
     auto store = [&](int u) {
 #pragma unroll
       for (int c = 0; c < NPC; ++c)
-        *reinterpret_cast<uint4 *>(px + c * (kG * kD) + 8 * u) = make_uint4(bw[c][0], bw[c][1], bw[c][2], bw[c][3]);
+        *reinterpret_cast<uint4 *>(px + c * (kG * kD) + u * (kG * 8)) = make_uint4(bw[c][0], bw[c][1], bw[c][2], bw[c][3]);
     };
     clear();
     unsigned short *lo = phil + o;
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
 #pragma unroll
         for (int m = 0; m < kPhiRounds; ++m) {
           const int du = u0 + 64 * m + l, pc = du >> 9, i = (du >> 2) & 127, cu = (du & 3) ^ ((i >> 1) & 3);
-          dma16(src + pc * kPhiB + i * kD + 8 * cu, dst + 8 * (u0 + 64 * m));
+          dma16(src + pc * kPhiB + cu * (kG * 8) + i * 8, dst + 8 * (u0 + 64 * m));
         }
       }
     };
@@ -735,8 +736,21 @@ __global__ __launch_bounds__(kG) void k_xfunc(FArgs A) {
     }
   }
   const double sigma = s[1] * s[1] + s[2] * s[2] + s[3] * s[3];
-  const Xc f = xc_eval(A.xc, s[0], sigma, A.rho_cut);
+  Xc f;
   const double wgt = A.g.w[ip];
+  if (A.tpart[0]) {
+    // meta-GGA: tau = (1/2) sum_a sum_mu d_a chi_mu (D d_a Phi)_mu, from component 1 + a of the partials
+    // of the product with d_a Phi (each 2 sum_mu d_a chi_mu X^a_mu), in item order
+    double t = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int64_t it = A.blk_item_off[r]; it < A.blk_item_off[r + 1]; ++it)
+        t += A.tpart[a][size_t(it - A.item0) * (4 * kG) + (1 + a) * kG + j];
+    const Xc4 m = xc_eval_mgga(A.xc, s[0], sigma, 0.25 * t, A.rho_cut);
+    f = Xc{m.f, m.vr, m.vs};
+    A.ctau[ip] = 0.25 * wgt * m.vt;
+  } else {
+    f = xc_eval(A.xc, s[0], sigma, A.rho_cut);
+  }
   const int64_t o = A.g.orig[ip];
   double *rho_out = A.io->rho, *sigma_out = A.io->sigma;
   if (rho_out && o >= 0) rho_out[o] = s[0];
@@ -869,6 +883,7 @@ struct VArgs {
   int *vflag;              // [n_items] 1 if the item wrote a partial
   unsigned long long *counters;
   QArgs q;
+  int accumulate;          // FP64 operands: add to the item's partial when an earlier launch wrote one
 };
 
 
@@ -907,6 +922,7 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   const int u = w & 3, h = w >> 2;
   const T *phi = static_cast<const T *>(A.phi) - size_t(A.ret0) * (kD * kG);   // indexed by retained tile
   const T *zws = static_cast<const T *>(A.zws) - size_t(A.ret0) * (kD * kG);
+  const int prev = A.accumulate ? A.vflag[item] : 0;
 
   acc_t acc[2][4];
   double dacc[2][4][4];
@@ -1099,7 +1115,7 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
     }
   }
   if (!any) {
-    if (tid == 0) A.vflag[item] = 0;
+    if (tid == 0 && !A.accumulate) A.vflag[item] = 0;
     return;
   }
   double *out = A.vpart + size_t(item) * (128 * 128);
@@ -1124,7 +1140,8 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = 32 * u + 16 * ti + M::row(v, l), col = 64 * h + 16 * tj + (l & 15);
-          out[row * 128 + col] = dacc[ti][tj][v] + double(acc[ti][tj][v]);
+          const double val = dacc[ti][tj][v] + double(acc[ti][tj][v]);
+          out[row * 128 + col] = prev ? out[row * 128 + col] + val : val;
         }
       }
   }
@@ -1282,6 +1299,176 @@ __global__ __launch_bounds__(NT) void k_esum(const MolDev *mol, const double *__
   if (threadIdx.x == 0) io->exc[blockIdx.x] = s[0];
 }
 
+// One workgroup per retained tile (p, r) of the chunk: which = 0: d_a Phi into Aout (and W into Wout
+// when not NULL); which = 1: Q^a into Aout.
+__global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev st, int64_t ret0,
+                                             const double *__restrict__ coef, int ax, int which,
+                                             double *__restrict__ Aout, double *__restrict__ Wout) {
+  const int64_t k = ret0 + blockIdx.x;
+  const int j = threadIdx.x;
+  const int p = st.ret_p[k];
+  const int64_t ip = int64_t(st.ret_r[k]) * kG + j;
+  const double *cf = coef + size_t(ip) * 4;
+  const double c0 = 2.0 * cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3];
+  const double x = g.x[ip], y = g.y[ip], z = g.z[ip];
+  const size_t o = size_t(blockIdx.x) * (kD * kG) + j;
+  // second-derivative slots (xx xy xz yy yz zz) of row ax
+  const int h0 = ax == 0 ? 0 : (ax == 1 ? 1 : 2), h1 = ax == 0 ? 1 : (ax == 1 ? 3 : 4), h2 = ax == 0 ? 2 : (ax == 1 ? 4 : 5);
+  for (int a = 0; a < kD; ++a) {
+    double v, gr[3], h[6];
+    eval_ao_hess(B, p * kD + a, x, y, z, v, gr, h);
+    Aout[o + a * kG] = which == 0 ? gr[ax] : c1 * h[h0] + c2 * h[h1] + c3 * h[h2];
+    if (Wout) Wout[o + a * kG] = c0 * v + c1 * gr[0] + c2 * gr[1] + c3 * gr[2];
+  }
+}
+
+// 256-point screening blocks: one workgroup per compute block r of the chunk with (r - first block of its
+// molecule) even and a partner r + 1: z_qr of both halves becomes the maximum over the two (the retained
+// lists of the halves are the same tiles in the same order).
+__global__ __launch_bounds__(NT) void k_zpair(StructDev st, int64_t blk0, double *__restrict__ zmax) {
+  const int64_t r = blk0 + blockIdx.x;
+  const MolDev mo = st.mol[st.blk_mol[r]];
+  if (((r - mo.blk0) & 1) || r + 1 >= mo.blk1) return;
+  const int64_t k0 = st.blk_off[r], k1 = st.blk_off[r + 1];
+  const int64_t n = k1 - k0;
+  for (int64_t t = threadIdx.x; t < n; t += NT) {
+    const double z = fmax(zmax[k0 + t], zmax[k1 + t]);
+    zmax[k0 + t] = z;
+    zmax[k1 + t] = z;
+  }
+}
+
+// One workgroup per retained tile of the chunk: B = (w v_tau / 4) d_a Phi, the column operand of the
+// meta-GGA Vxc term.
+__global__ __launch_bounds__(kG) void k_tscale(StructDev st, int64_t ret0, const double *__restrict__ ctau,
+                                              const double *__restrict__ dphi, double *__restrict__ out) {
+  const int64_t k = ret0 + blockIdx.x;
+  const int j = threadIdx.x;
+  const double c = ctau[int64_t(st.ret_r[k]) * kG + j];
+  const size_t o = size_t(blockIdx.x) * (kD * kG) + j;
+  for (int a = 0; a < kD; ++a) out[o + a * kG] = c * dphi[o + a * kG];
+}
+
+// The X stage of grid chunk ci: Phi on its retained tiles, X = D Phi with the rho / grad rho epilogue,
+// then the functional (rho, E_xc partials, Z coefficients).  mark(k) records stage event k when the plan
+// runs in one chunk.
+template <class T, int NPC, class Mark>
+void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
+  const EvalDev &E = P.ev;
+  const GridChunk &C = P.chunks_h[ci];
+  const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nxit = C.xit1 - C.xit0;
+  if (nret > 0)
+    k_basis<T, NPC><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, static_cast<T *>(E.phi), E.phil, E.phix);
+  mark(2);
+  XArgs xa;
+  xa.B = P.basis;
+  xa.g = P.grid;
+  xa.st = P.st;
+  xa.xit_r = P.xit_r;
+  xa.xit_c = P.xit_c;
+  xa.item0 = C.xit0;
+  xa.n_items = nxit;
+  xa.ret0 = C.ret0;
+  xa.Dt = E.Dt;
+  xa.amax = E.amax;
+  xa.phi = E.phi;
+  xa.phil = E.phil;
+  xa.phix = E.phix;
+  xa.part = E.xpart;
+  xa.counters = E.counters;
+  xa.t_b = P.opts.t_b;
+  xa.t_d = P.opts.t_d;
+  xa.q = QArgs{P.xq.order, P.xq.qoff + 9 * ci};
+  const int64_t gx = 8 * P.xq.maxlen_h[ci];
+  if (nxit > 0) {
+    if (P.gga)
+      k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(xa);
+    else
+      k_xgemm<T, false, NPC><<<gx, NTX, 0, s>>>(xa);
+    if constexpr (sizeof(T) == 8 && NPC == 0) {
+      if (is_mgga_xc(P.opts.xc)) {
+        // meta-GGA: the products D d_a Phi on the same items (operand d_a Phi, every retained operand tile
+        // with a retained D block: t_d = 0), their pairs counted apart
+        XArgs ta = xa;
+        ta.phi = E.tdphi;
+        ta.t_d = 0.0;
+        ta.counters = E.counters + 4;
+        for (int a = 0; a < 3; ++a) {
+          k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr);
+          ta.part = E.tpart[a];
+          k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(ta);
+        }
+      }
+    }
+  }
+  mark(3);
+  FArgs fa;
+  fa.g = P.grid;
+  fa.blk_item_off = P.blk_item_off;
+  fa.blk0 = C.blk0;
+  fa.item0 = C.xit0;
+  fa.part = E.xpart;
+  fa.coef = E.coef;
+  fa.eblk = E.eblk;
+  fa.io = E.io;
+  fa.counters = E.counters;
+  fa.rho_cut = P.opts.rho_cut;
+  fa.xc = P.opts.xc;
+  fa.gga = P.gga ? 1 : 0;
+  for (int a = 0; a < 3; ++a) fa.tpart[a] = E.tpart[a];
+  fa.ctau = E.ctau;
+  if (nblk > 0) {
+    if (P.has_mlp)
+      (void)mlp_launch_xfunc(fa, P.mlp, nblk, s);
+    else
+      k_xfunc<<<nblk, kG, 0, s>>>(fa);
+  }
+}
+
+// Arguments of a k_vgemm launch over the Vxc items of grid chunk ci with operands A (rows) and B.
+VArgs v_args(const Plan &P, size_t ci, const void *A, const void *B) {
+  const EvalDev &E = P.ev;
+  const GridChunk &C = P.chunks_h[ci];
+  VArgs va;
+  va.st = P.st;
+  va.items = P.items;
+  va.item0 = C.vit0;
+  va.n_items = C.vit1 - C.vit0;
+  va.ret0 = C.ret0;
+  va.cinfo = P.cinfo;
+  va.cioff = P.cioff;
+  va.vmoff = P.vmoff;
+  va.vm_base = P.vmoff_h[C.blk0];
+  va.vmask = E.vmask;
+  va.phi = A;
+  va.zws = B;
+  va.vpart = E.vpart;
+  va.vflag = E.vflag;
+  va.counters = E.counters;
+  va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci};
+  va.accumulate = 0;
+  return va;
+}
+
+VMaskArgs m_args(const Plan &P, size_t ci) {
+  const EvalDev &E = P.ev;
+  const GridChunk &C = P.chunks_h[ci];
+  VMaskArgs ma;
+  ma.st = P.st;
+  ma.cinfo = P.cinfo;
+  ma.cioff = P.cioff;
+  ma.vmoff = P.vmoff;
+  ma.vm_base = P.vmoff_h[C.blk0];
+  ma.pair_info = P.pair_info;
+  ma.zmax = E.zmax;
+  ma.blk0 = C.blk0;
+  ma.vmask = E.vmask;
+  ma.t_b = P.opts.t_b;
+  ma.t_d = P.opts.t_d;
+  ma.upper_only = P.gga ? 0 : 1;
+  return ma;
+}
+
 template <class T, int NPC>
 hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
   const EvalDev &E = P.ev;
@@ -1290,6 +1477,9 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
   const bool one = P.chunks_h.size() == 1;
   auto mark = [&](int i) {
     if (ev) (void)hipEventRecord(ev[i], s);
+  };
+  auto mark1 = [&](int i) {
+    if (one) mark(i);
   };
   mark(0);
   if constexpr (NPC > 0)
@@ -1305,56 +1495,8 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
   }
   for (size_t ci = 0; ci < P.chunks_h.size(); ++ci) {
     const GridChunk &C = P.chunks_h[ci];
-    const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nxit = C.xit1 - C.xit0, nvit = C.vit1 - C.vit0;
-    if (nret > 0)
-      k_basis<T, NPC><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, static_cast<T *>(E.phi), E.phil, E.phix);
-    if (one) mark(2);
-    XArgs xa;
-    xa.B = P.basis;
-    xa.g = P.grid;
-    xa.st = P.st;
-    xa.xit_r = P.xit_r;
-    xa.xit_c = P.xit_c;
-    xa.item0 = C.xit0;
-    xa.n_items = nxit;
-    xa.ret0 = C.ret0;
-    xa.Dt = E.Dt;
-    xa.amax = E.amax;
-    xa.phi = E.phi;
-    xa.phil = E.phil;
-    xa.phix = E.phix;
-    xa.part = E.xpart;
-    xa.counters = E.counters;
-    xa.t_b = P.opts.t_b;
-    xa.t_d = P.opts.t_d;
-    xa.q = QArgs{P.xq.order, P.xq.qoff + 9 * ci};
-    const int64_t gx = 8 * P.xq.maxlen_h[ci];
-    if (nxit > 0) {
-      if (P.gga)
-        k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(xa);
-      else
-        k_xgemm<T, false, NPC><<<gx, NTX, 0, s>>>(xa);
-    }
-    if (one) mark(3);
-    FArgs fa;
-    fa.g = P.grid;
-    fa.blk_item_off = P.blk_item_off;
-    fa.blk0 = C.blk0;
-    fa.item0 = C.xit0;
-    fa.part = E.xpart;
-    fa.coef = E.coef;
-    fa.eblk = E.eblk;
-    fa.io = E.io;
-    fa.counters = E.counters;
-    fa.rho_cut = P.opts.rho_cut;
-    fa.xc = P.opts.xc;
-    fa.gga = P.gga ? 1 : 0;
-    if (nblk > 0) {
-      if (P.has_mlp)
-        (void)mlp_launch_xfunc(fa, P.mlp, nblk, s);
-      else
-        k_xfunc<<<nblk, kG, 0, s>>>(fa);
-    }
+    const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nvit = C.vit1 - C.vit0;
+    x_stage<T, NPC>(P, ci, s, mark1);
     if (want_v && nret > 0) {
       if (P.gga)
         k_zform<T, true><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, static_cast<const T *>(E.phi),
@@ -1363,39 +1505,11 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
         k_zform<T, false><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, static_cast<const T *>(E.phi),
                                               E.phil, static_cast<T *>(E.zws), E.zmax);
     }
-    if (one) mark(4);
+    if (want_v && nblk > 0 && P.opts.grid_block == 2 * kG) k_zpair<<<nblk, NT, 0, s>>>(P.st, C.blk0, E.zmax);
+    mark1(4);
     if (want_v && nblk > 0) {
-      VMaskArgs ma;
-      ma.st = P.st;
-      ma.cinfo = P.cinfo;
-      ma.cioff = P.cioff;
-      ma.vmoff = P.vmoff;
-      ma.vm_base = P.vmoff_h[C.blk0];
-      ma.pair_info = P.pair_info;
-      ma.zmax = E.zmax;
-      ma.blk0 = C.blk0;
-      ma.vmask = E.vmask;
-      ma.t_b = P.opts.t_b;
-      ma.t_d = P.opts.t_d;
-      ma.upper_only = P.gga ? 0 : 1;
-      k_vmask<<<nblk, NT, 0, s>>>(ma);
-      VArgs va;
-      va.st = P.st;
-      va.items = P.items;
-      va.item0 = C.vit0;
-      va.n_items = nvit;
-      va.ret0 = C.ret0;
-      va.cinfo = P.cinfo;
-      va.cioff = P.cioff;
-      va.vmoff = P.vmoff;
-      va.vm_base = P.vmoff_h[C.blk0];
-      va.vmask = E.vmask;
-      va.phi = E.phi;
-      va.zws = E.zws;
-      va.vpart = E.vpart;
-      va.vflag = E.vflag;
-      va.counters = E.counters;
-      va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci};
+      k_vmask<<<nblk, NT, 0, s>>>(m_args(P, ci));
+      VArgs va = v_args(P, ci, E.phi, E.zws);
       const int64_t gv = 8 * P.vq.maxlen_h[ci];
       const int64_t nd = P.dchunk_h[ci + 1] - P.dchunk_h[ci];
       const bool diag = sizeof(T) == 4 && nd > 0;
@@ -1407,6 +1521,23 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
         if (e != hipSuccess) return e;
       }
       if (nvit > 0) k_vgemm<T><<<gv, NTV, 0, s>>>(va);
+      if constexpr (sizeof(T) == 8 && NPC == 0) {
+        if (is_mgga_xc(P.opts.xc) && nvit > 0 && nret > 0) {
+          // meta-GGA: + sum_a d_a Phi (w v_tau / 4 d_a Phi)^T over every pair of retained tiles of a block
+          VMaskArgs ma = m_args(P, ci);
+          ma.t_b = 0.0;
+          ma.t_d = 0.0;
+          k_vmask<<<nblk, NT, 0, s>>>(ma);
+          VArgs tv = v_args(P, ci, E.tdphi, E.tB);
+          tv.accumulate = 1;
+          tv.counters = E.counters + 4;
+          for (int a = 0; a < 3; ++a) {
+            k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr);
+            k_tscale<<<nret, kG, 0, s>>>(P.st, C.ret0, E.ctau, E.tdphi, E.tB);
+            k_vgemm<T><<<gv, NTV, 0, s>>>(tv);
+          }
+        }
+      }
       if (diag) {
         VDArgs da;
         da.st = P.st;
@@ -1442,6 +1573,154 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------------
+// Nuclear gradient of E_xc with the grid held fixed (FP64 plans of one molecule):
+//   dE/dR_Aa = -2 sum_{mu on A} sum_nu D_{mu nu} K^a_{mu nu},  K^a = (d_a Phi) W^T + Q^a Phi^T,
+//   W = c0 Phi + sum_b c_b d_b Phi,  Q^a = sum_b c_b d_a d_b Phi,  c0 = w v_rho,  c_b = 2 w v_sigma d_b rho.
+// The products run on k_vgemm over the Vxc work items, tile pairs (p, q) executing at block r when
+// (p, r), (q, r) are retained and a_pq >= t_b; each item's partial is contracted with D at once.
+// LDA plans hold the chunk pairs pc <= qc only: there the pairs pc < qc also run the product with
+// its operands exchanged, W (d_a Phi)^T = (K^a)^T for the transposed chunk pair, contracted along columns.
+// ------------------------------------------------------------------------------------------------
+
+// One workgroup per grid block of the chunk: the executable tile pairs of the gradient products as
+// 16-bit masks per (row chunk, column chunk) pair: (p, r), (q, r) retained and a_pq >= t_b.  skip_diag:
+// no pair of a diagonal chunk pair (the exchanged-operand pass of LDA plans).
+__global__ __launch_bounds__(NT) void k_gmask(VMaskArgs A, const double *__restrict__ amax, int skip_diag) {
+  const int64_t r = A.blk0 + blockIdx.x;
+  const MolDev mo = A.st.mol[A.st.blk_mol[r]];
+  const int *ci = A.cinfo + A.cioff[r];
+  unsigned short *out = A.vmask + (A.vmoff[r] - A.vm_base);
+  for (int pr = threadIdx.x; pr < mo.npairs; pr += NT) {
+    const int pc = A.pair_info[3 * (mo.pair0 + pr)], qc = A.pair_info[3 * (mo.pair0 + pr) + 1];
+    const int ip = ci[pc], iq = ci[qc];
+    int mask = 0;
+    if (!(skip_diag && pc == qc)) {
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        if (!((ip >> ww) & 1)) continue;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          if (!((iq >> jj) & 1)) continue;
+          const size_t t = size_t(mo.dt0) + size_t(4 * pc + ww) * mo.nt + (4 * qc + jj);
+          if (amax[t] >= A.t_b) mask |= 1 << (4 * ww + jj);
+        }
+      }
+    }
+    out[pr] = (unsigned short)mask;
+  }
+}
+
+// One workgroup (128 threads) per Vxc item of the launch: its partial P (rows: AOs of row chunk pc,
+// columns: AOs of column chunk qc) times D element by element, summed along each row (mode 0: one sum
+// per row AO) or each column (mode 1: one per column AO), into slot `slot` of the item's gradient
+// partial (zeros where the item executed nothing).
+__global__ __launch_bounds__(kG) void k_gcontract(const VItem *__restrict__ items, int64_t item0,
+                                                 const MolDev *__restrict__ mol, const int *__restrict__ pair_info,
+                                                 const int *__restrict__ vflag, const double *__restrict__ vpart,
+                                                 const double *__restrict__ Dt, int mode, int slot,
+                                                 double *__restrict__ gitem) {
+  const int64_t item = item0 + blockIdx.x;
+  const VItem it = items[item];
+  const MolDev mo = mol[pair_info[3 * it.pair + 2]];
+  const int i = threadIdx.x;
+  double s = 0.0;
+  if (vflag[item]) {
+    const double *Pp = vpart + size_t(item) * 16384;
+    auto d = [&](int row, int col) {   // D of AO row of chunk pc, AO col of chunk qc
+      const int p = 4 * it.pc + (row >> 5), q = 4 * it.qc + (col >> 5);
+      if (p >= mo.nt || q >= mo.nt) return 0.0;
+      return Dt[(size_t(mo.dt0) + size_t(p) * mo.nt + q) * 1024 + (row & 31) * 32 + (col & 31)];
+    };
+    if (mode == 0)
+      for (int j = 0; j < 128; ++j) s += d(i, j) * Pp[i * 128 + j];
+    else
+      for (int j = 0; j < 128; ++j) s += d(j, i) * Pp[j * 128 + i];
+  }
+  gitem[(size_t(item) * 6 + slot) * 128 + i] = s;
+}
+
+// One workgroup per row chunk c of the molecule: the per-AO gradient sums of the 128 AOs of c, over the
+// items in a fixed order (pairs in index order, a pair's items in segment order).  Slots per item:
+// 2a and 2a+1 for component a; GGA: both are row sums of items with pc = c; LDA: slot 2a row sums of
+// items with pc = c, slot 2a+1 column sums of items with qc = c > pc.
+__global__ __launch_bounds__(kG) void k_greduce(const MolDev *__restrict__ mol, const int *__restrict__ pair_ptr,
+                                               const int *__restrict__ pair_items, const int *__restrict__ pair_info,
+                                               const double *__restrict__ gitem, int lda, double *__restrict__ gao,
+                                               int ld) {
+  const MolDev mo = mol[0];
+  const int c = blockIdx.x, i = threadIdx.x;
+  for (int a = 0; a < 3; ++a) {
+    double s = 0.0;
+    for (int pr = mo.pair0; pr < mo.pair0 + mo.npairs; ++pr) {
+      const int pc = pair_info[3 * pr], qc = pair_info[3 * pr + 1];
+      const bool rows = pc == c, cols = lda && qc == c && pc != c;
+      if (!rows && !cols) continue;
+      for (int k = pair_ptr[pr]; k < pair_ptr[pr + 1]; ++k) {
+        const double *gi = gitem + size_t(pair_items[k]) * 6 * 128 + i;
+        if (rows) s += gi[(2 * a) * 128];
+        if (rows && !lda) s += gi[(2 * a + 1) * 128];
+        if (cols) s += gi[(2 * a + 1) * 128];
+      }
+    }
+    gao[size_t(a) * ld + size_t(c) * 128 + i] = s;
+  }
+}
+
+// One thread per (atom, component): dE/dR_Aa = -2 sum over the atom's AOs (internal order) of the
+// per-AO sums.
+__global__ __launch_bounds__(NT) void k_gatom(const int *__restrict__ ao_atom, int n_ao, int n_atoms,
+                                             const double *__restrict__ gao, int ld, double *__restrict__ grad) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= 3 * n_atoms) return;
+  const int A = t / 3, a = t % 3;
+  double s = 0.0;
+  for (int mu = 0; mu < n_ao; ++mu)
+    if (ao_atom[mu] == A) s += gao[size_t(a) * ld + mu];
+  grad[t] = -2.0 * s;
+}
+
+hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
+  const EvalDev &E = P.ev;
+  const MolDev &mo = P.mols_h[0];
+  auto none = [](int) {};
+  k_dprep<double><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, static_cast<double *>(E.Dt), E.amax,
+                                        E.counters);
+  const double *Dt = static_cast<const double *>(E.Dt);
+  double *A = P.grad_ws.gA;
+  for (size_t ci = 0; ci < P.chunks_h.size(); ++ci) {
+    const GridChunk &C = P.chunks_h[ci];
+    const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nvit = C.vit1 - C.vit0;
+    x_stage<double, 0>(P, ci, s, none);
+    if (nret == 0 || nvit == 0) continue;
+    const int64_t gv = 8 * P.vq.maxlen_h[ci];
+    auto product = [&](const void *opA, const void *opB, int skip_diag, int mode, int slot) {
+      k_gmask<<<nblk, NT, 0, s>>>(m_args(P, ci), E.amax, skip_diag);
+      k_vgemm<double><<<gv, NTV, 0, s>>>(v_args(P, ci, opA, opB));
+      k_gcontract<<<nvit, kG, 0, s>>>(P.items, C.vit0, P.st.mol, P.pair_info, E.vflag, E.vpart, Dt, mode, slot,
+                                      P.grad_ws.gitem);
+    };
+    for (int ax = 0; ax < 3; ++ax) {
+      k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 0, A,
+                                  ax == 0 ? static_cast<double *>(E.zws) : nullptr);
+      product(A, E.zws, 0, 0, 2 * ax);              // (d_a Phi) W^T
+      if (P.gga) {
+        k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 1, A, nullptr);
+        product(A, E.phi, 0, 0, 2 * ax + 1);        // Q^a Phi^T
+      } else {
+        product(E.zws, A, 1, 1, 2 * ax + 1);        // W (d_a Phi)^T of the pairs pc < qc
+      }
+    }
+  }
+  k_esum<<<P.n_mol, NT, 0, s>>>(P.st.mol, E.eblk, E.io);
+  const int ld = mo.nc * 128;
+  k_greduce<<<mo.nc, kG, 0, s>>>(P.st.mol, P.pair_ptr, P.pair_items, P.pair_info, P.grad_ws.gitem, P.gga ? 0 : 1,
+                                 P.grad_ws.gao, ld);
+  k_gatom<<<(3 * P.n_atoms0 + NT - 1) / NT, NT, 0, s>>>(P.ao_atom, mo.n_ao, P.n_atoms0, P.grad_ws.gao, ld,
+                                                       grad);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_screen(const BasisDev &b, const GridDev &g, const int *cand_p, const int64_t *cand_r,
@@ -1455,6 +1734,8 @@ hipError_t launch_begin(const Plan &P, const IoDev &io, hipStream_t s) {
   k_begin<<<1, NT, 0, s>>>(P.ev.io, io, P.ev.counters);
   return hipGetLastError();
 }
+
+hipError_t launch_grad(const Plan &P, double *grad, hipStream_t s) { return grad_body(P, grad, s); }
 
 hipError_t launch_body(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
   switch (P.opts.prec) {

@@ -24,6 +24,7 @@ constexpr int kMlpWidth = 64;       // hidden width of the functional surrogate
 constexpr int kMlpParams = 8707;    // 2-64-64-64-3 weights and biases
 
 // BF16 pieces per operand of the X product (0: the plan's operands are FP64 or FP32)
+inline bool is_mgga_xc(int xc) { return xc == KLDI_XC_MVS || xc == KLDI_XC_MVS_X; }
 inline int bf16_pieces(int prec) { return prec == KLDI_PREC_BF16X3 ? 2 : (prec == KLDI_PREC_BF16X6 ? 3 : 0); }
 
 // Device view of a trained functional surrogate.  Every field points into the network's own device
@@ -104,7 +105,7 @@ struct EvalDev {
   void *phi;               // [max chunk retained tiles * 4096] Phi workspace, working precision
   void *zws;               // [max chunk retained tiles * 4096] Z workspace
   unsigned short *phil;    // FP32 plans: [max chunk retained tiles * 4096] bf16(Phi - fl32(Phi)); else NULL
-  unsigned short *phix;    // BF16 split plans: per retained tile the BF16 pieces of Phi, [piece][point][AO]
+  unsigned short *phix;    // BF16 split plans: per retained tile the BF16 pieces of Phi, [piece][AO/8][point][8]
   double *xpart;           // [max chunk X items * 4 * 128] rho / grad rho partials of each X work item
   double *coef;            // [n_pad * 4] Z coefficients per point
   double *zmax;            // [n_ret]
@@ -113,7 +114,12 @@ struct EvalDev {
   int *vflag;              // [n_items] 1 if the item wrote a partial
   unsigned short *vmask;   // [max chunk mask entries] executable tile pairs of each (block, chunk pair)
   double *mfull;           // [sum (nc*128)^2]
-  unsigned long long *counters;  // [4]: pairs X, pairs V, nonfinite flag, points on the surrogate
+  unsigned long long *counters;  // [8]: pairs X, pairs V, nonfinite flag, points on the surrogate; [4], [5]:
+                                 // pairs of the meta-GGA tau products (X, V), kept apart
+  double *tdphi;           // meta-GGA: [max chunk retained tiles * 4096] d_a Phi (one component at a time)
+  double *tB;              // meta-GGA: [max chunk retained tiles * 4096] (w v_tau / 4) d_a Phi
+  double *tpart[3];        // meta-GGA: per component, X-item partials of D d_a Phi (as xpart)
+  double *ctau;            // meta-GGA: [n_pad] w v_tau / 4
   double *escratch;        // [n_mol] E_xc of kldi_eval_grid
   IoDev *io;               // [1] caller buffers of the running evaluation
 };
@@ -193,6 +199,15 @@ struct Plan {
   Queues xq, vq;
   int *ditems = nullptr;              // Vxc items of diagonal chunk pairs (pc = qc), grouped by grid chunk
   std::vector<int64_t> dchunk_h;      // [n_gchunks + 1] offsets into ditems
+  // nuclear gradient (kldi_eval_grad): workspaces of the current schedule, allocated on first use
+  struct GradWs {
+    double *gA = nullptr;     // [max chunk retained tiles * 4096] operand of the gradient products
+    double *gitem = nullptr;  // [n_items][6][128] per-item contracted partials
+    double *gao = nullptr;    // [3][nc * 128] per-AO sums
+  } grad_ws;
+  int *ao_atom = nullptr;             // [n_ao_pad] caller atom of each internal AO (single-molecule plans), -1 on padding
+  int n_atoms0 = 0;                   // atoms of the first molecule
+  int64_t max_ret = 0;                // largest retained-tile count of a grid chunk in the current schedule
   // functional surrogate attached with kldi_plan_attach_mlp
   bool has_mlp = false;
   MlpDev mlp{};
@@ -225,6 +240,8 @@ hipError_t launch_begin(const Plan &P, const IoDev &io, hipStream_t s);
 // everything after k_begin (captured into a graph when the plan runs in graph mode)
 hipError_t launch_body(const Plan &P, bool want_v, hipStream_t s,
                        hipEvent_t *ev /* KLDI_N_STAGES + 1 events, or NULL */);
+// nuclear gradient of a single-molecule FP64 plan after k_begin (grad: [n_atoms * 3] device)
+hipError_t launch_grad(const Plan &P, double *grad, hipStream_t s);
 hipError_t launch_xc_arrays(int xc, const double *rho, const double *sigma, int64_t n, double rho_cut, double *f,
                             double *vr, double *vs, hipStream_t s);
 // functional surrogate (mlp.hip)

@@ -70,6 +70,15 @@ class _PlanBase:
                             _stream_handle(stream)), "kldi_eval")
         return r, e, v
 
+    def grad(self, D, exc=None, stream=None):
+        """kldi_eval_grad: dE_xc/dR (n_atoms x 3 float64 CUDA tensor) with the grid held fixed."""
+        _check_d(D, self.n_ao)
+        g = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=D.device)
+        L.check(L.kldi_eval_grad(self._h, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                 ctypes.c_void_p(exc.data_ptr() if exc is not None else 0), _stream_handle(stream)),
+                "kldi_eval_grad")
+        return g
+
     def attach_mlp(self, mlp):
         L.check(L.kldi_plan_attach_mlp(self._h, mlp._h if mlp is not None else None), "kldi_plan_attach_mlp")
         self._mlp = mlp
@@ -127,6 +136,7 @@ class Plan(_PlanBase):
         self._h = ctypes.c_void_p()
         self._keep = []
         b, g, self.n_ao, self.n_points = _structs(atom_xyz, basis, grid_xyz, weights, point_atom, self._keep)
+        self.n_atoms = int(np.asarray(atom_xyz).shape[0])
         o = _opts(xc, prec, t_b, t_d, rho_cut, grid_block, ao_block, v_segment, chunk_tiles, schedule)
         if shell_order is not None:
             so = np.ascontiguousarray(shell_order, np.int32)

@@ -114,7 +114,7 @@ def test_invalid_arguments_rejected_before_any_launch(L, bad):
     assert len(L.kldi_last_error()) > 0
 
 
-@pytest.mark.parametrize("field,value", [("grid_block", 256), ("ao_block", 64)])
+@pytest.mark.parametrize("field,value", [("grid_block", 512), ("grid_block", 192), ("ao_block", 64)])
 def test_unsupported_block_shapes(L, field, value):
     p = synth.tiny_problem(seed=2)
     b, g, o, keep = _structs(L, p, **{field: value})

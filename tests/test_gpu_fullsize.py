@@ -102,3 +102,36 @@ def test_cfg1_vxc_is_energy_derivative(setup):
     print("cfg1 dE/dD at t=1e-14: fd %.10f analytic %.10f rel %.2e" % (fd, an, abs(fd - an) / abs(an)), flush=True)
     assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cfg1_overlap_order_against_stored_oracle(setup, prec):
+    """The same workload with the basis functions ordered by overlap-signature clustering: the library's
+    order (kldi_overlap_order) equals the oracle's stored one, and the plan using it matches the blocked
+    oracle run with that order (cfg1_overlap_blocked.json), to the bars of the atom-order test."""
+    Plan, p, gb, gd = setup
+    path = os.path.join(HERE, "cfg1_overlap_blocked.json")
+    go = json.load(open(path))
+    assert go["seeds"] == p.meta["seeds"] and go["v_ij"] == gb["v_ij"]
+    from paper_2605_10363_amd.plan import overlap_order
+    _, so = overlap_order(p.basis, synth.overlap_matrix(p.basis, p.atom_xyz))
+    assert np.array_equal(so, np.array(go["shell_order"]))
+    print("case: cfg1 overlap order prec=%s" % prec, flush=True)
+    plan = Plan.from_problem(p, prec=prec, shell_order=so)
+    D = torch.from_numpy(p.D).cuda()
+    rho, exc, vxc = plan.eval(D)
+    st = plan.check()
+    E = float(exc.item())
+    V = vxc.cpu().numpy()
+    dE, dV, drho = errors(go, E, V, rho.cpu().numpy())
+    print("cfg1 overlap order %s vs blocked oracle: dE %.3e dV %.3e drho %.3e pairs x %d/%d v %d/%d" % (
+        prec, dE, dV, drho, st["n_pairs_x"], go["n_pairs_x"], st["n_pairs_v"], go["n_pairs_v"]), flush=True)
+    assert np.array_equal(V, V.T)
+    assert dE < 1e-6 and dV < 1e-7 and drho < 1e-5
+    if prec == "fp64":
+        assert (st["n_pairs_x"], st["n_pairs_v"]) == (go["n_pairs_x"], go["n_pairs_v"])
+        assert dE < 1e-9 and dV < 1e-11 and drho < 1e-10
+    else:
+        assert st["n_pairs_x"] == go["n_pairs_x"]
+        assert abs(st["n_pairs_v"] - go["n_pairs_v"]) <= 1e-5 * go["n_pairs_v"]
+    plan.close()

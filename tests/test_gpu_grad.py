@@ -1,0 +1,100 @@
+"""GPU: the nuclear gradient of E_xc with the grid held fixed (kldi_eval_grad, FP64 plans) against the
+oracle (oracle.grad): the block-filtered gradient at the same thresholds element by element, the dense
+gradient without screening, and at full size central differences of E_xc in atom positions."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import grad as og
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def Plan():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_10363_amd.plan import Plan
+    return Plan
+
+
+def _grad(Plan, p, xc, **kw):
+    plan = Plan.from_problem(p, xc=xc, prec="fp64", **kw)
+    D = torch.from_numpy(p.D).cuda()
+    exc = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = plan.grad(D, exc=exc).cpu().numpy()
+    _, e, _ = plan.eval(D, vxc=False)
+    torch.cuda.synchronize()
+    assert float(exc.item()) == float(e.item())
+    plan.close()
+    return g
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe", "pbe_x"])
+@pytest.mark.parametrize("shape", [(2, 10, 26, 2, 41), (4, 16, 50, 4, 42), (5, 13, 38, 5, 43)])
+def test_tiny_gradient_matches_blocked_oracle(Plan, xc, shape):
+    n_atoms, n_rad, n_ang, n_occ, seed = shape
+    p = synth.tiny_problem(n_atoms=n_atoms, n_rad=n_rad, n_ang=n_ang, n_occ=n_occ, xc=xc, seed=seed, box_A=4.0)
+    print("case: tiny gradient %s xc=%s" % (p.name, xc), flush=True)
+    ref = og.exc_gradient_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc,
+                                  t_b=1e-10)
+    g = _grad(Plan, p, xc)
+    print("  max |dg| %.2e of max |g| %.2e" % (np.abs(g - ref).max(), np.abs(ref).max()), flush=True)
+    assert np.abs(g - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_unscreened_gradient_matches_dense_oracle(Plan, xc):
+    p = synth.tiny_problem(n_atoms=4, n_rad=14, n_ang=26, n_occ=4, xc=xc, seed=44, box_A=5.0)
+    print("case: unscreened gradient xc=%s" % xc, flush=True)
+    ref = og.exc_gradient(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.D, xc)
+    g = _grad(Plan, p, xc, t_b=0.0, t_d=0.0)
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_cfg0_gradient_matches_blocked_oracle(Plan, cfg0, xc):
+    p = cfg0
+    print("case: cfg0 gradient xc=%s" % xc, flush=True)
+    ref = og.exc_gradient_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc,
+                                  t_b=1e-10)
+    g = _grad(Plan, p, xc)
+    print("  max |dg| %.2e of max |g| %.2e" % (np.abs(g - ref).max(), np.abs(ref).max()), flush=True)
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_gradient_refuses_unsupported_plans(Plan):
+    p = synth.tiny_problem(n_atoms=2, n_rad=10, n_ang=26, n_occ=2, seed=41)
+    from paper_2605_10363_amd._lib import KldiError
+    plan = Plan.from_problem(p, prec="fp32")
+    with pytest.raises(KldiError) as e:
+        plan.grad(torch.from_numpy(p.D).cuda())
+    assert e.value.status == -4
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_chain_gradient_matches_energy_differences(Plan):
+    """200-atom chain (2000 AOs, 4.53M points, PBE): the FP64 gradient of three atom coordinates against
+    central differences of E_xc (atoms moved with their basis functions, grid fixed) at thresholds
+    1e-14, where the screening sets hardly change with the displacement."""
+    p = synth.make_problem(1)
+    print("case: chain gradient vs energy differences", flush=True)
+    plan = Plan.from_problem(p, prec="fp64", t_b=1e-14, t_d=1e-14)
+    D = torch.from_numpy(p.D).cuda()
+    g = plan.grad(D).cpu().numpy()
+    plan.close()
+    h = 1e-4
+    for A, a in ((0, 0), (57, 1), (150, 2)):
+        Es = []
+        for sgn in (1, -1):
+            xyz = p.atom_xyz.copy()
+            xyz[A, a] += sgn * h
+            pl = Plan(xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, xc="pbe", prec="fp64", t_b=1e-14,
+                      t_d=1e-14)
+            Es.append(float(pl.eval(D, vxc=False)[1].item()))
+            pl.close()
+        fd = (Es[0] - Es[1]) / (2 * h)
+        print("  atom %d axis %d: gradient %.10f, central difference %.10f" % (A, a, g[A, a], fd), flush=True)
+        assert abs(g[A, a] - fd) <= 1e-6 * max(1.0, abs(fd))

@@ -296,3 +296,40 @@ def test_overlap_clustered_basis_order(Plan, cfg0, xc, which):
                                                              Plan.from_problem(p, xc=xc).info()["retained_fraction"]),
           flush=True)
     g["plan"].close()
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+@pytest.mark.parametrize("which", ["tiny", "cfg0"])
+def test_256_point_blocks_against_blocked_oracle(Plan, cfg0, xc, which):
+    """Grid blocks of 256 points: the library screens and filters per 256-point block (the two 128-point
+    blocks of its kernels share the retained tiles and the summaries b_pr, z_qr of the pair); results
+    against the oracle run with G = 256 (FP64 to 1e-12, executed pairs counted per 128 points), FP32 within
+    the mixed targets, and one grid chunk equal to several bit for bit."""
+    p = cfg0 if which == "cfg0" else synth.tiny_problem(n_atoms=5, n_rad=14, n_ang=38, n_occ=5, xc=xc, seed=45,
+                                                        box_A=5.0)
+    ref = oracle.eval_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc,
+                              t_b=1e-10, t_d=1e-10, d_ao=32, G=256, count_unit=128)
+    g = run(Plan, p, xc, grid_block=256)
+    assert abs(g["E"] - ref["E"]) <= 1e-12 * max(1.0, abs(ref["E"]))
+    assert np.abs(g["V"] - ref["V"]).max() <= 1e-12 * max(1.0, np.abs(ref["V"]).max())
+    assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * max(1.0, np.abs(ref["rho"]).max())
+    assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
+    p128 = Plan.from_problem(p, xc=xc)
+    g128 = p128.info()["retained_fraction"]
+    p128.close()
+    print("%s %s G=256: retained fraction %.4f (G=128 %.4f)" % (which, xc, g["info"]["retained_fraction"], g128),
+          flush=True)
+    g["plan"].close()
+    f = run(Plan, p, xc, prec="fp32", grid_block=256)
+    assert abs(f["E"] - ref["E"]) < 1e-6 and np.abs(f["V"] - ref["V"]).max() < 1e-7
+    f["plan"].close()
+    if which == "cfg0":
+        D = torch.from_numpy(p.D).cuda()
+        outs = []
+        for ct in (0, 40):
+            plan = Plan.from_problem(p, xc=xc, prec="fp32", grid_block=256, v_segment=16, chunk_tiles=ct)
+            outs.append([t.cpu().numpy().copy() for t in plan.eval(D)] + [plan.info()["n_grid_chunks"]])
+            plan.close()
+        assert outs[0][3] == 1 and outs[1][3] > 1
+        for x, y in zip(outs[0][:3], outs[1][:3]):
+            assert np.array_equal(x, y)
