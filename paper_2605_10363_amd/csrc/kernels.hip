@@ -719,6 +719,209 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   });
 }
 
+constexpr int NTX4 = 256;   // threads per FP32 X workgroup: 4 waves, wave u owns output tile u (32 rows x 128 points)
+
+// FP32 operands: one workgroup of 4 waves per (grid block r, chunk c of 4 retained output tiles), the
+// same items and results as k_xgemm.  Its LDS (78 KB: a two-slot ring of one compacted entry each,
+// 4 D tiles + one Phi tile, which the epilogue's FP64 X of two tiles overlays) lets two workgroups share
+// a CU, so one workgroup's copies, barriers and epilogue overlap the other's MFMAs.  Wave u multiplies
+// D_(p_u, q) (32 x 32) by Phi_qr (32 x 128) on v_mfma_f32_16x16x4f32: MFMA step kk takes k = 8 (l / 16) + kk,
+// output column c of sub-tile tj is point 8 c + tj, so a lane reads its 8 values of a row of Phi_q with
+// two 16-byte loads.  The FP32 accumulators of sub-tile row ti are added to the FP64 sums once per 32
+// values of k (row 0 after step 3, row 1 after step 7 of each entry, so the two rows' flushes alternate
+// with MFMAs).
+template <bool GGA>
+__global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
+  typedef Mma<float> M;
+  constexpr int kEnt = 4 * kD * kD + kD * kG;   // floats per ring slot (32 KB)
+  __shared__ __align__(16) float ring[2 * kEnt];
+  __shared__ int s_p[kMaxNp];
+  __shared__ int s_list[kMaxNp];
+  __shared__ int s_q[kMaxNp];
+  __shared__ int s_w[4];
+  __shared__ double s_acc[2][4][kG];
+  static_assert(2 * kD * kG * sizeof(double) <= sizeof(ring), "epilogue X exceeds the ring");
+  run_items(A.q, A.item0, [&](int64_t il) {
+  const int64_t it = A.item0 + il;
+  const int64_t r = A.xit_r[it];
+  const int c = A.xit_c[it];
+  const int tid = threadIdx.x, l = tid & 63;
+  const int ws = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m16 = l & 15, g = l >> 4;
+  const MolDev mo = A.st.mol[A.st.blk_mol[r]];
+  const int64_t k0 = A.st.blk_off[r];
+  const int np = int(A.st.blk_off[r + 1] - k0);
+  const float *Df = static_cast<const float *>(A.Dt);
+  const float *phi = static_cast<const float *>(A.phi) - size_t(A.ret0) * (kD * kG);   // by retained tile
+  auto dtile = [&](int p, int q) { return size_t(mo.dt0) + size_t(p - mo.tile0) * mo.nt + (q - mo.tile0); };
+
+  for (int t = tid; t < np; t += NTX4) s_p[t] = A.st.ret_p[k0 + t];
+  __syncthreads();
+
+  // ---- executable pairs of this chunk (eq. block_pair_filter), compacted by exclusive prefix sums
+  // over the workgroup (Appendix D), NTX4 candidates per round
+  unsigned long long pairs = 0;
+  int n_list = 0;
+  for (int base = 0; base < np; base += NTX4) {
+    const int t = base + tid;
+    int mask = 0;
+    if (t < np) {
+      const int q = s_p[t];
+      const double bq = A.st.bphi[k0 + t];
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        if (4 * c + ww < np) {
+          const double a = A.amax[dtile(s_p[4 * c + ww], q)];
+          if (a >= A.t_b && a * bq >= A.t_d) mask |= 1 << ww;
+        }
+      }
+    }
+    int tot;
+    const int pos = n_list + block_scan(mask != 0, s_w, &tot);
+    if (mask) {
+      s_list[pos] = t | (mask << 16);
+      s_q[pos] = s_p[t];
+      pairs += __popc(mask);
+    }
+    n_list += tot;
+  }
+  __syncthreads();
+
+  // ---- X_(p_u) r = sum over the compacted q of D_(p_u) q Phi_qr
+  f4 acc[2][8];
+  double dacc[2][8][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 8; ++tj) {
+      acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dacc[ti][tj][v] = 0.0;
+    }
+  // D tile row of this wave's output tile: a slot past the end of S_r uses entry np - 1 (valid memory,
+  // never multiplied: its wave has no executable pair)
+  const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + ws, np - 1)]);
+  const float *Drow = Df + dtile(pa, mo.tile0) * (kD * kD);
+  // entry e goes to slot e % 2: wave w copies D_(p_w, q) as [row i][k] with the 16-byte units of row i
+  // XOR-swizzled (unit c at c ^ (i & 7)), and quarter w of Phi_q as [k][point], global -> LDS directly
+  auto issue = [&](int e) {
+    float *dst = ring + (e & 1) * kEnt;
+    const int q = __builtin_amdgcn_readfirstlane(s_q[e]);
+    const float *src = Drow + size_t(q - mo.tile0) * (kD * kD);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+      dma16(src + i * kD + 4 * cu, dst + ws * (kD * kD) + 256 * m);
+    }
+    const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
+    const float *ps = phi + size_t(k0 + t) * (kD * kG) + 1024 * ws;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dma16(ps + 4 * (64 * m + l), dst + 4 * kD * kD + 1024 * ws + 256 * m);
+  };
+  auto flush = [&](int ti) {
+#pragma unroll
+    for (int tj = 0; tj < 8; ++tj) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
+      acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  if (n_list > 0) issue(0);
+  // entry e: wait until this wave's copies of e have landed and its reads of e - 1 are done; after the
+  // barrier the slot of e - 1 takes e + 1
+  for (int e = 0; e < n_list; ++e) {
+    wait_vm_lds<0>();
+    wg_barrier();
+    if (e + 1 < n_list) issue(e + 1);
+    if ((__builtin_amdgcn_readfirstlane(s_list[e] >> 16) >> ws) & 1) {
+      const float *se = ring + (e & 1) * kEnt;
+      f4 a[2][2];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+          a[ti][hh] = *reinterpret_cast<const f4 *>(se + ws * (kD * kD) + (16 * ti + m16) * kD +
+                                                    4 * ((2 * g + hh) ^ (m16 & 7)));
+      const float *sb = se + 4 * kD * kD + 8 * m16;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const f4 b0 = *reinterpret_cast<const f4 *>(sb + (8 * g + kk) * kG);
+        const f4 b1 = *reinterpret_cast<const f4 *>(sb + (8 * g + kk) * kG + 4);
+        const float a0 = a[0][kk >> 2][kk & 3], a1 = a[1][kk >> 2][kk & 3];
+#pragma unroll
+        for (int tj = 0; tj < 8; ++tj) {
+          const float bv = tj < 4 ? b0[tj] : b1[tj - 4];
+          acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
+          acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
+        }
+        if (kk == 3) flush(0);
+        if (kk == 7) flush(1);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- epilogue: rho_i += sum_mu Phi_mu,i X_mu,i and grad rho_i += 2 sum_mu grad Phi_mu,i X_mu,i over
+  // the AOs of the chunk's tiles, two tiles per round: their X (FP64) goes through LDS, then one thread
+  // per (tile, point) evaluates the tile's shells in FP64 (a wave shares one tile, so the shell data are
+  // scalar loads); the per-point sums are ((tile 0 + tile 1) + (tile 2 + tile 3)).
+  double *Xs = reinterpret_cast<double *>(ring);   // [2][kD][kG]
+  const int slot_w = tid >> 7, j = tid & (kG - 1);
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int R = 0; R < 2; ++R) {
+    if ((ws >> 1) == R && 4 * c + ws < np) {
+      double *Xw = Xs + (ws & 1) * (kD * kG);
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 8; ++tj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            Xw[(16 * ti + M::row(v, l)) * kG + 8 * m16 + tj] = dacc[ti][tj][v] + double(acc[ti][tj][v]);
+    }
+    __syncthreads();
+    const int slot = 4 * c + 2 * R + slot_w;
+    double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    if (slot < np) {
+      const double *Xw = Xs + slot_w * (kD * kG);
+      if (GGA) {
+        const int64_t ip = r * kG + j;
+        const int pt = __builtin_amdgcn_readfirstlane(s_p[slot]);
+        for_tile_aos<true>(A.B, pt, A.g.x[ip], A.g.y[ip], A.g.z[ip], [&](int a, double v, double gx, double gy,
+                                                                          double gz) {
+          const double X = Xw[a * kG + j];
+          s0 += v * X;
+          sx += gx * X;
+          sy += gy * X;
+          sz += gz * X;
+        });
+      } else {
+        const float *ph = phi + size_t(k0 + slot) * (kD * kG) + j;
+        const unsigned short *pl = A.phil + size_t(k0 + slot - A.ret0) * (kD * kG) + j;
+        for (int a = 0; a < kD; ++a) s0 += (double(ph[a * kG]) + from_bf16(pl[a * kG])) * Xw[a * kG + j];
+      }
+    }
+    s_acc[slot_w][0][j] = s0;
+    s_acc[slot_w][1][j] = 2.0 * sx;
+    s_acc[slot_w][2][j] = 2.0 * sy;
+    s_acc[slot_w][3][j] = 2.0 * sz;
+    __syncthreads();
+    if (tid < kG) {
+#pragma unroll
+      for (int cp = 0; cp < 4; ++cp) tot[cp] += s_acc[0][cp][tid] + s_acc[1][cp][tid];
+    }
+  }
+  if (tid < kG) {
+    double *out = A.part + size_t(il) * (4 * kG);
+#pragma unroll
+    for (int cp = 0; cp < (GGA ? 4 : 1); ++cp) out[cp * kG + tid] = tot[cp];
+  }
+  double pd = wave_sum(double(pairs));
+  if (l == 0 && pd > 0) atomicAdd(&A.counters[0], (unsigned long long)(pd + 0.5));
+  });
+}
+
 // One workgroup per grid block: rho and grad rho as fixed-order FP64 sums over the chunk partials,
 // the functional, the block's E_xc partial, rho in caller order, and the Z coefficients.
 __global__ __launch_bounds__(kG) void k_xfunc(FArgs A) {
@@ -1381,10 +1584,17 @@ void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
   xa.q = QArgs{P.xq.order, P.xq.qoff + 9 * ci};
   const int64_t gx = 8 * P.xq.maxlen_h[ci];
   if (nxit > 0) {
-    if (P.gga)
-      k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(xa);
-    else
-      k_xgemm<T, false, NPC><<<gx, NTX, 0, s>>>(xa);
+    if constexpr (sizeof(T) == 4 && NPC == 0) {
+      if (P.gga)
+        k_xgemm_f32<true><<<gx, NTX4, 0, s>>>(xa);
+      else
+        k_xgemm_f32<false><<<gx, NTX4, 0, s>>>(xa);
+    } else {
+      if (P.gga)
+        k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(xa);
+      else
+        k_xgemm<T, false, NPC><<<gx, NTX, 0, s>>>(xa);
+    }
     if constexpr (sizeof(T) == 8 && NPC == 0) {
       if (is_mgga_xc(P.opts.xc)) {
         // meta-GGA: the products D d_a Phi on the same items (operand d_a Phi, every retained operand tile

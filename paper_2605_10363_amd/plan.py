@@ -72,7 +72,7 @@ class _PlanBase:
 
     def grad(self, D, exc=None, stream=None):
         """kldi_eval_grad: dE_xc/dR (n_atoms x 3 float64 CUDA tensor) with the grid held fixed."""
-        _check_d(D, self.n_ao)
+        _check_d(D, self.n_ao * self.n_ao)
         g = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=D.device)
         L.check(L.kldi_eval_grad(self._h, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(g.data_ptr()),
                                  ctypes.c_void_p(exc.data_ptr() if exc is not None else 0), _stream_handle(stream)),

@@ -586,10 +586,15 @@ def batch_member(n_atoms, j, n_rad=50, n_ang=194, xc="lda", becke_cutoff=8.0):
     n_occ = max(1, int(round(basis.n_ao / 10.0)))
     D = make_density(np.random.default_rng(3000000 + j), S, n_occ)
     return Problem(name="mol%d" % j, atom_xyz=xyz, atom_heavy=heavy, basis=basis, grid=grid, D=D, n_occ=n_occ,
-                   xc=xc, grid_block=128,
-                   meta=dict(recipe=dict(kind="cube", n_heavy=n_heavy, n_light=n_atoms - n_heavy, box_A=box,
-                                         n_rad=n_rad, n_ang=n_ang, becke_cutoff=becke_cutoff),
-                             seeds=[1000000 + j, 2000000 + j, 3000000 + j], generator=GENERATOR_VERSION))
+                   xc=xc, grid_block=128, meta=_member_meta(n_atoms, j, n_rad, n_ang, becke_cutoff))
+
+
+def _member_meta(n_atoms, j, n_rad, n_ang, becke_cutoff):
+    n_heavy = int(round(n_atoms / 3.0))
+    box = 8.0 * (n_atoms / 12.0) ** (1.0 / 3.0)
+    return dict(recipe=dict(kind="cube", n_heavy=n_heavy, n_light=n_atoms - n_heavy, box_A=box, n_rad=n_rad,
+                            n_ang=n_ang, becke_cutoff=becke_cutoff),
+                seeds=[1000000 + j, 2000000 + j, 3000000 + j], generator=GENERATOR_VERSION)
 
 
 def batch_sizes(n_mol=256, atoms=(5, 60), seed=4003):
@@ -611,8 +616,8 @@ def make_batch(n_mol=None, atoms=None, n_rad=None, n_ang=None, xc="lda", cache=T
                            ).hexdigest()[:16]
         path = os.path.join(_cache_dir(), "batch_%s.npz" % key)
         if cache and os.path.exists(path):
-            p = _load(path, {})
-            p.xc = xc
+            p = _load(path, _member_meta(int(n), j, r["n_rad"], r["n_ang"], r["becke_cutoff"]))
+            p.name, p.xc = "mol%d" % j, xc
         else:
             p = batch_member(int(n), j, r["n_rad"], r["n_ang"], xc, r["becke_cutoff"])
             if cache:
