@@ -336,6 +336,18 @@ kldi_status kldi_mlp_loss_grad(kldi_mlp *mlp, const float *x_dev, const float *t
 kldi_status kldi_mlp_step(kldi_mlp *mlp, const float *x_dev, const float *t_dev, int64_t n, double lr,
                           double *loss_host, void *stream);
 
+/* Allocation-free form of kldi_mlp_step, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training loops, harnesses that forbid hipMalloc).  The same kernels and
+ * results as kldi_mlp_step (identical parameters, moments and loss), but the per-workgroup partial
+ * gradients live in a static device array of the library (8.9 MB, one per GPU, held until the process
+ * ends) instead of memory allocated per call, so: n <= 16384 points per call (larger n is rejected
+ * with KLDI_E_ARG); calls that overlap on one GPU (concurrent streams, threads) race on that array
+ * and must be serialised by the caller; nothing is allocated and the stream is not synchronised.
+ * *loss_dev (device, may be NULL) receives the batch loss before the step.  The step count used for
+ * the bias corrections advances on the host at each call. */
+kldi_status kldi_mlp_step_static(kldi_mlp *mlp, const float *x_dev, const float *t_dev, int64_t n, double lr,
+                                 double *loss_dev, void *stream);
+
 /* Basis-function order by overlap-signature clustering (Sec. III-B.2, "Locality-Preserving
  * Reordering"; appendix on reordering details, eqs. overlap_signature, cosine_similarity,
  * cosine_distance).  Row i of the overlap matrix is the signature of basis function i; functions are

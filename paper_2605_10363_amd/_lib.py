@@ -125,6 +125,9 @@ kldi_mlp_loss_grad = _sig("kldi_mlp_loss_grad", ctypes.c_int,
 kldi_mlp_step = _sig("kldi_mlp_step", ctypes.c_int,
                      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                       ctypes.c_void_p, ctypes.c_void_p])
+kldi_mlp_step_static = _sig("kldi_mlp_step_static", ctypes.c_int,
+                            [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                             ctypes.c_void_p, ctypes.c_void_p])
 kldi_eval_grad = _sig("kldi_eval_grad", ctypes.c_int,
                       [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p])
 kldi_overlap_order = _sig("kldi_overlap_order", ctypes.c_int,
@@ -140,7 +143,7 @@ EXPORTS = sorted(["kldi_opts_default", "kldi_plan_create", "kldi_batch_create", 
                   "kldi_plan_graph", "kldi_plan_autotune", "kldi_plan_destroy", "kldi_plan_info",
                   "kldi_plan_structure", "kldi_eval", "kldi_eval_check", "kldi_plan_timing", "kldi_eval_timing",
                   "kldi_eval_grid", "kldi_xc_eval", "kldi_mlp_create", "kldi_mlp_destroy", "kldi_mlp_train",
-                  "kldi_mlp_forward", "kldi_mlp_loss_grad", "kldi_mlp_step", "kldi_mlp_params", "kldi_overlap_order", "kldi_eval_grad", "kldi_plan_attach_mlp",
+                  "kldi_mlp_forward", "kldi_mlp_loss_grad", "kldi_mlp_step", "kldi_mlp_step_static", "kldi_mlp_params", "kldi_overlap_order", "kldi_eval_grad", "kldi_plan_attach_mlp",
                   "kldi_last_error", "kldi_version"])
 STAGES = ["dprep", "basis", "xgemm", "xfunc", "vgemm", "vfinal"]
 

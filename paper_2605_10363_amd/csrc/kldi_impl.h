@@ -38,6 +38,7 @@ struct MlpDev {
                                   // the analytic functional is used)
 };
 constexpr int kMlpStats = 11;
+constexpr int64_t kMlpStaticMaxPoints = 16384;   // batch limit of the allocation-free training step
 
 // A plan holds one molecule or a batch of independent molecules in one index space: the AO tiles,
 // grid blocks, retained tiles and work items of all molecules are numbered consecutively, and every
@@ -250,6 +251,10 @@ hipError_t mlp_launch_grad(const float *theta, const float *x, const float *t, i
 hipError_t mlp_launch_adam(float *theta, float *m, float *v, void *theta_b, const float *gpart, int n_wg, float lr,
                            int step, float *grad_out, hipStream_t s);
 hipError_t mlp_launch_tobf16(const float *theta, void *theta_b, hipStream_t s);
+// one Adam step with the partial gradients in the library's static scratch (n <= kMlpStaticMaxPoints)
+hipError_t mlp_launch_step_static(float *theta, float *m, float *v, void *theta_b, const float *x, const float *t,
+                                  int64_t n, float lr, int step, double *loss, hipStream_t s);
+size_t mlp_static_scratch_bytes();
 hipError_t mlp_launch_loss_sum(const double *lpart, int n, double *out, hipStream_t s);
 hipError_t mlp_launch_flags(const double *rho, int64_t n, double rho_min, int *flag, int *blk_count, hipStream_t s);
 hipError_t mlp_launch_compact(const double *rho, const double *sigma, int64_t n, const int *flag, const int64_t *blk_off,

@@ -7,6 +7,8 @@
 // [-1, 1].  Outputs: three standardised heads y; t = y * t_std + t_mean are f / rho^(4/3),
 // v_rho / rho^(1/3) and v_sigma * rho^(4/3).  Points with rho < rho_min or features outside the box
 // fall back to the analytic functional.
+#include <mutex>
+
 #include <hip/hip_bf16.h>
 
 #include "device.h"
@@ -204,6 +206,20 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *theta, float *m, float 
   const float th = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   theta[i] = th;
   theta_b[i] = __float2bfloat16(th);
+}
+
+// the batch-mean loss of n points from the workgroup shares, written (not accumulated) to *out
+__global__ __launch_bounds__(256) void k_loss_mean(const double *lpart, int n_wg, int64_t n, double *out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n_wg; i += 256) a += lpart[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0] / (3.0 * double(n));
 }
 
 __global__ __launch_bounds__(256) void k_mlp_tobf16(const float *theta, __hip_bfloat16 *theta_b) {
@@ -513,6 +529,41 @@ __global__ __launch_bounds__(256) void k_xc_arrays(int xc, const double *rho, co
 
 }  // namespace
 
+// ---- the allocation-free training step's scratch: the per-workgroup partial gradients and loss
+// shares of one batch of at most kMlpStaticMaxPoints points, in a file-scope device array.  Each GPU
+// holds its own copy until the process ends; its address on the current device is taken once with
+// hipGetSymbolAddress (the array's name is only a host-side stand-in) and kept per device.
+constexpr int kStaticWg = int(kMlpStaticMaxPoints / TP);
+constexpr size_t kScratchGrad = size_t(kStaticWg) * kMlpParams * sizeof(float);
+constexpr size_t kScratchBytes = kScratchGrad + size_t(kStaticWg) * sizeof(double);
+static_assert(kMlpStaticMaxPoints % TP == 0 && kScratchGrad % 8 == 0, "scratch layout");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first call per device)
+hipError_t scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+size_t mlp_static_scratch_bytes() { return kScratchBytes; }
+
 // ---- launchers (declared in kldi_impl.h)
 hipError_t mlp_launch_grad(const float *theta, const float *x, const float *t, int64_t n, int64_t start, int64_t count,
                            int64_t pa, int64_t pb, float *gpart, double *lpart, hipStream_t s) {
@@ -527,6 +578,23 @@ hipError_t mlp_launch_adam(float *theta, float *m, float *v, void *theta_b, cons
   const float c1 = 1.f - powf(0.9f, float(step)), c2 = 1.f - powf(0.999f, float(step));
   k_mlp_adam<<<(kMlpParams + 255) / 256, 256, 0, s>>>(theta, m, v, static_cast<__hip_bfloat16 *>(theta_b), gpart, n_wg,
                                                      lr, c1, c2, grad_out);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_step_static(float *theta, float *m, float *v, void *theta_b, const float *x, const float *t,
+                                  int64_t n, float lr, int step, double *loss, hipStream_t s) {
+  if (n < 1 || n > kMlpStaticMaxPoints) return hipErrorInvalidValue;
+  void *base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return e;
+  float *gpart = static_cast<float *>(base);
+  double *lpart = reinterpret_cast<double *>(static_cast<unsigned char *>(base) + kScratchGrad);
+  const int nwg = int((n + TP - 1) / TP);
+  e = mlp_launch_grad(theta, x, t, n, 0, n, 1, 0, gpart, lpart, s);
+  if (e != hipSuccess) return e;
+  e = mlp_launch_adam(theta, m, v, theta_b, gpart, nwg, lr, step, nullptr, s);
+  if (e != hipSuccess || !loss) return e;
+  k_loss_mean<<<1, 256, 0, s>>>(lpart, nwg, n, loss);
   return hipGetLastError();
 }
 

@@ -230,6 +230,26 @@ kldi_status kldi_mlp_step(kldi_mlp *M, const float *x, const float *t, int64_t n
   return st;
 }
 
+kldi_status kldi_mlp_step_static(kldi_mlp *M, const float *x, const float *t, int64_t n, double lr, double *loss,
+                                 void *stream) {
+  if (!M || !x || !t || n < 1 || !(lr > 0)) {
+    kldi::set_error("bad arguments to kldi_mlp_step_static");
+    return KLDI_E_ARG;
+  }
+  if (n > kldi::kMlpStaticMaxPoints) {
+    kldi::set_error("kldi_mlp_step_static takes at most " + std::to_string(kldi::kMlpStaticMaxPoints) +
+                    " points per call (the size of its static scratch)");
+    return KLDI_E_ARG;
+  }
+  return run([&] {
+    hipc(hipSetDevice(M->device), "hipSetDevice");
+    ++M->step;
+    hipc(kldi::mlp_launch_step_static(M->theta, M->m, M->v, M->theta_b, x, t, n, float(lr), M->step, loss,
+                                      static_cast<hipStream_t>(stream)),
+         "step");
+  });
+}
+
 kldi_status kldi_mlp_train(kldi_mlp *M, const double *rho, const double *sigma, int64_t n, const kldi_train_cfg *cfg,
                            double *loss_host, void *stream) {
   if (!M || !rho || !sigma || n < 1 || !cfg || cfg->epochs < 0 || cfg->batch < 1 || !(cfg->lr > 0) ||

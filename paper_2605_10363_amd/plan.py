@@ -297,6 +297,13 @@ class Mlp:
                                 float(lr), ctypes.byref(loss), _stream_handle(stream)), "kldi_mlp_step")
         return loss.value
 
+    def step_static(self, x, t, lr, loss=None, stream=None):
+        """kldi_mlp_step_static: the same step without device allocation (n <= 16384); the loss before
+        the step goes to `loss` (a float64 CUDA tensor of one element) if given.  Does not synchronise."""
+        L.check(L.kldi_mlp_step_static(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                       x.shape[0], float(lr), ctypes.c_void_p(loss.data_ptr() if loss is not None else 0),
+                                       _stream_handle(stream)), "kldi_mlp_step_static")
+
     def train(self, rho, sigma, epochs=10, batch=65536, lr=2e-3, seed=1, xc="pbe", rho_min=1e-8, stream=None):
         cfg = L.kldi_train_cfg(int(epochs), int(batch), float(lr), int(seed), L.XC[xc], float(rho_min))
         losses = np.zeros(max(int(epochs), 1))
