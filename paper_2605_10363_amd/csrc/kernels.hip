@@ -922,6 +922,181 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
   });
 }
 
+// FP64 operands: the 4-wave X kernel of k_xgemm_f32 on v_mfma_f64_16x16x4f64, the same items and results
+// as k_xgemm.  An FP64 entry (64 KB) is taken in two K halves of 16 values, each a ring slot of 32 KB
+// (4 D half-tiles [row i][k] with the 16-byte units of row i XOR-swizzled, unit c at c ^ (i & 7), and
+// half of Phi_q as [k][point]); MFMA step kk of a half takes k = 4 (l / 16) + kk.  The accumulators are
+// FP64, so X needs no flush.
+template <bool GGA>
+__global__ __launch_bounds__(NTX4, 2) void k_xgemm_f64(XArgs A) {
+  typedef Mma<double> M;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  constexpr int kHalf = kD / 2;                       // K values per sub-step
+  constexpr int kSub = 4 * kD * kHalf + kHalf * kG;   // doubles per ring slot (32 KB)
+  __shared__ __align__(16) double ring[2 * kSub];
+  __shared__ int s_p[kMaxNp];
+  __shared__ int s_list[kMaxNp];
+  __shared__ int s_q[kMaxNp];
+  __shared__ int s_w[4];
+  __shared__ double s_acc[2][4][kG];
+  static_assert(2 * kD * kG <= 2 * kSub, "epilogue X exceeds the ring");
+  run_items(A.q, A.item0, [&](int64_t il) {
+  const int64_t it = A.item0 + il;
+  const int64_t r = A.xit_r[it];
+  const int c = A.xit_c[it];
+  const int tid = threadIdx.x, l = tid & 63;
+  const int ws = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m16 = l & 15, g = l >> 4;
+  const MolDev mo = A.st.mol[A.st.blk_mol[r]];
+  const int64_t k0 = A.st.blk_off[r];
+  const int np = int(A.st.blk_off[r + 1] - k0);
+  const double *Dd = static_cast<const double *>(A.Dt);
+  const double *phi = static_cast<const double *>(A.phi) - size_t(A.ret0) * (kD * kG);   // by retained tile
+  auto dtile = [&](int p, int q) { return size_t(mo.dt0) + size_t(p - mo.tile0) * mo.nt + (q - mo.tile0); };
+
+  for (int t = tid; t < np; t += NTX4) s_p[t] = A.st.ret_p[k0 + t];
+  __syncthreads();
+
+  unsigned long long pairs = 0;
+  int n_list = 0;
+  for (int base = 0; base < np; base += NTX4) {
+    const int t = base + tid;
+    int mask = 0;
+    if (t < np) {
+      const int q = s_p[t];
+      const double bq = A.st.bphi[k0 + t];
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        if (4 * c + ww < np) {
+          const double a = A.amax[dtile(s_p[4 * c + ww], q)];
+          if (a >= A.t_b && a * bq >= A.t_d) mask |= 1 << ww;
+        }
+      }
+    }
+    int tot;
+    const int pos = n_list + block_scan(mask != 0, s_w, &tot);
+    if (mask) {
+      s_list[pos] = t | (mask << 16);
+      s_q[pos] = s_p[t];
+      pairs += __popc(mask);
+    }
+    n_list += tot;
+  }
+  __syncthreads();
+
+  d4 acc[2][8];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 8; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
+  const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + ws, np - 1)]);
+  const double *Drow = Dd + dtile(pa, mo.tile0) * (kD * kD);
+  // sub-step st = 2 e + h: K half h of entry e, into slot st % 2; wave w copies D_(p_w, q) and quarter w
+  // of the half of Phi_q, global -> LDS directly
+  auto issue = [&](int st) {
+    const int e = st >> 1, h = st & 1;
+    double *dst = ring + (st & 1) * kSub;
+    const int q = __builtin_amdgcn_readfirstlane(s_q[e]);
+    const double *src = Drow + size_t(q - mo.tile0) * (kD * kD) + kHalf * h;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+      dma16(src + i * kD + 2 * cu, dst + ws * (kD * kHalf) + 128 * m);
+    }
+    const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
+    const double *ps = phi + size_t(k0 + t) * (kD * kG) + (kHalf * kG) * h + 512 * ws;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dma16(ps + 2 * (64 * m + l), dst + 4 * kD * kHalf + 512 * ws + 128 * m);
+  };
+  const int nst = 2 * n_list;
+  if (nst > 0) issue(0);
+  for (int st = 0; st < nst; ++st) {
+    wait_vm_lds<0>();
+    wg_barrier();
+    if (st + 1 < nst) issue(st + 1);
+    if ((__builtin_amdgcn_readfirstlane(s_list[st >> 1] >> 16) >> ws) & 1) {
+      const double *se = ring + (st & 1) * kSub;
+      d2 a[2][2];
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+          a[ti][hh] = *reinterpret_cast<const d2 *>(se + ws * (kD * kHalf) + (16 * ti + m16) * kHalf +
+                                                    2 * ((2 * g + hh) ^ (m16 & 7)));
+      const double *sb = se + 4 * kD * kHalf + 8 * m16;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        d2 b[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) b[jj] = *reinterpret_cast<const d2 *>(sb + (4 * g + kk) * kG + 2 * jj);
+        const double a0 = a[0][kk >> 1][kk & 1], a1 = a[1][kk >> 1][kk & 1];
+#pragma unroll
+        for (int tj = 0; tj < 8; ++tj) {
+          const double bv = b[tj >> 1][tj & 1];
+          acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
+          acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- epilogue as in k_xgemm_f32
+  double *Xs = ring;   // [2][kD][kG]
+  const int slot_w = tid >> 7, j = tid & (kG - 1);
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int R = 0; R < 2; ++R) {
+    if ((ws >> 1) == R && 4 * c + ws < np) {
+      double *Xw = Xs + (ws & 1) * (kD * kG);
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 8; ++tj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Xw[(16 * ti + M::row(v, l)) * kG + 8 * m16 + tj] = acc[ti][tj][v];
+    }
+    __syncthreads();
+    const int slot = 4 * c + 2 * R + slot_w;
+    double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    if (slot < np) {
+      const double *Xw = Xs + slot_w * (kD * kG);
+      if (GGA) {
+        const int64_t ip = r * kG + j;
+        const int pt = __builtin_amdgcn_readfirstlane(s_p[slot]);
+        for_tile_aos<true>(A.B, pt, A.g.x[ip], A.g.y[ip], A.g.z[ip], [&](int a, double v, double gx, double gy,
+                                                                          double gz) {
+          const double X = Xw[a * kG + j];
+          s0 += v * X;
+          sx += gx * X;
+          sy += gy * X;
+          sz += gz * X;
+        });
+      } else {
+        const double *ph = phi + size_t(k0 + slot) * (kD * kG) + j;
+        for (int a = 0; a < kD; ++a) s0 += ph[a * kG] * Xw[a * kG + j];
+      }
+    }
+    s_acc[slot_w][0][j] = s0;
+    s_acc[slot_w][1][j] = 2.0 * sx;
+    s_acc[slot_w][2][j] = 2.0 * sy;
+    s_acc[slot_w][3][j] = 2.0 * sz;
+    __syncthreads();
+    if (tid < kG) {
+#pragma unroll
+      for (int cp = 0; cp < 4; ++cp) tot[cp] += s_acc[0][cp][tid] + s_acc[1][cp][tid];
+    }
+  }
+  if (tid < kG) {
+    double *out = A.part + size_t(il) * (4 * kG);
+#pragma unroll
+    for (int cp = 0; cp < (GGA ? 4 : 1); ++cp) out[cp * kG + tid] = tot[cp];
+  }
+  double pd = wave_sum(double(pairs));
+  if (l == 0 && pd > 0) atomicAdd(&A.counters[0], (unsigned long long)(pd + 0.5));
+  });
+}
+
 // One workgroup per grid block: rho and grad rho as fixed-order FP64 sums over the chunk partials,
 // the functional, the block's E_xc partial, rho in caller order, and the Z coefficients.
 __global__ __launch_bounds__(kG) void k_xfunc(FArgs A) {
@@ -1354,6 +1529,293 @@ __global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
   });
 }
 
+constexpr int NTV4 = 256;   // threads per FP32 Vxc workgroup: 4 waves, wave a owns row tile a (32 x 128)
+
+// FP32 operands: one workgroup of 4 waves per Vxc item (row chunk pc, column chunk qc, segment of grid
+// blocks), the same items and results as k_vgemm: M_pq = sum_r Phi_pr Z_qr^T over the executable grid
+// blocks of the segment, compacted by prefix sum.  Its LDS (69 KB: a two-slot ring of one 32-point
+// sub-step each, 4 Phi slabs and 4 Z slabs of 32 x 32) lets two workgroups share a CU, so one
+// workgroup's copies, barriers and compaction overlap the other's MFMAs.  Wave a multiplies the Phi slab
+// of row tile a by the 4 Z slabs; MFMA step kk takes point 8 (l / 16) + kk of the sub-step, so a lane
+// reads the 8 values of its row of a slab with two 16-byte loads.  The FP32 accumulators of a column tile
+// are added to the FP64 sums after each sub-step (32 points).  The diagonal pairs (a, a) of a diagonal
+// chunk pair are k_vdiag's (FP64).
+__global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
+  typedef Mma<float> M;
+  constexpr int kSP = 32, kNS = kG / kSP, kSlab = kD * kSP, kSlot = 8 * kSlab;
+  __shared__ __align__(16) float ring[2 * kSlot];
+  __shared__ int s_m[NTV4];
+  __shared__ int s_ip[NTV4], s_iq[NTV4];
+  __shared__ long long s_bo[NTV4];
+  __shared__ int s_w[4];
+  run_items(A.q, A.item0, [&](int64_t il) {
+  const int64_t item = A.item0 + il;
+  const VItem it = A.items[item];
+  const int tid = threadIdx.x, l = tid & 63;
+  const int ws = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m16 = l & 15, g = l >> 4;
+  const float *Pf = static_cast<const float *>(A.phi) - size_t(A.ret0) * (kD * kG);   // by retained tile
+  const float *Zf = static_cast<const float *>(A.zws) - size_t(A.ret0) * (kD * kG);
+  const bool diag = it.pc == it.qc;
+
+  f4 acc[2][8];
+  double dacc[2][8][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 8; ++tj) {
+      acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dacc[ti][tj][v] = 0.0;
+    }
+  unsigned long long pairs = 0;
+  int any = 0;
+  for (int base = it.r0; base < it.r1; base += NTV4) {
+    const int r = base + tid;
+    int mask = 0;
+    if (r < it.r1) mask = A.vmask[A.vmoff[r] - A.vm_base + it.lpair];
+    int tot;
+    const int pos = block_scan(mask != 0, s_w, &tot);
+    if (mask) {
+      s_m[pos] = mask;
+      const int64_t cb = A.cioff[r];
+      s_ip[pos] = A.cinfo[cb + it.pc];
+      s_iq[pos] = A.cinfo[cb + it.qc];
+      s_bo[pos] = A.st.blk_off[r];
+      pairs += __popc(mask);
+    }
+    __syncthreads();
+    any |= tot;
+    // sub-step st = kNS e + sub: entry e of the compacted list, points kSP sub .. kSP sub + kSP - 1.  Slot
+    // st % 2: slab a < 4 is Phi_(4pc+a), slab 4 + b is Z_(4qc+b), each [row i][point] with the 16-byte
+    // units of row i XOR-swizzled (unit c at c ^ (i & 7)); wave w copies slabs w and 4 + w, global -> LDS
+    // directly, one sub-step ahead, and only where the slab's tile has an executable pair.
+    const int nst = kNS * tot;
+    auto issue = [&](int st) {
+      const int e = st / kNS, sub = st % kNS;
+      const int m = __builtin_amdgcn_readfirstlane(s_m[e]);
+      const long long bo = s_bo[e];
+      float *dst = ring + (st & 1) * kSlot;
+      if ((m >> (4 * ws)) & 15) {
+        const int info = __builtin_amdgcn_readfirstlane(s_ip[e]);
+        const float *src = Pf + size_t(bo + tile_pos(info, ws)) * (kD * kG) + kSP * sub;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          dma16(src + i * kG + 4 * cu, dst + ws * kSlab + 256 * k);
+        }
+      }
+      if ((m >> ws) & 0x1111) {
+        const int info = __builtin_amdgcn_readfirstlane(s_iq[e]);
+        const float *src = Zf + size_t(bo + tile_pos(info, ws)) * (kD * kG) + kSP * sub;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          dma16(src + i * kG + 4 * cu, dst + (4 + ws) * kSlab + 256 * k);
+        }
+      }
+    };
+    if (nst > 0) issue(0);
+    for (int st = 0; st < nst; ++st) {
+      // this wave's copies of sub-step st have landed and its reads of st - 1 are done; after the
+      // barrier the slot of st - 1 takes sub-step st + 1
+      wait_vm_lds<0>();
+      wg_barrier();
+      if (st + 1 < nst) issue(st + 1);
+      const int m = (__builtin_amdgcn_readfirstlane(s_m[st / kNS]) >> (4 * ws)) & ((diag ? ~(1 << ws) : 15) & 15);
+      if (m) {
+        const float *sl = ring + (st & 1) * kSlot;
+        f4 fa[2][2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh)
+            fa[t][hh] = *reinterpret_cast<const f4 *>(sl + ws * kSlab + (16 * t + m16) * kSP +
+                                                      4 * ((2 * g + hh) ^ (m16 & 7)));
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if (!((m >> b) & 1)) continue;
+          f4 fb[2][2];
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+              fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + (16 * t + m16) * kSP +
+                                                        4 * ((2 * g + hh) ^ (m16 & 7)));
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+              for (int tj = 0; tj < 2; ++tj)
+                acc[ti][2 * b + tj] = M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3], acc[ti][2 * b + tj]);
+          // FP32 sums of 32 points each, FP64 beyond
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) dacc[ti][2 * b + tj][v] += double(acc[ti][2 * b + tj][v]);
+              acc[ti][2 * b + tj] = f4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!any) {
+    if (tid == 0 && !A.accumulate) A.vflag[item] = 0;
+    return;
+  }
+  double *out = A.vpart + size_t(item) * (128 * 128);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (diag && b == ws) continue;           // written by k_vdiag
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 32 * ws + 16 * ti + M::row(v, l), col = 32 * b + 16 * tj + m16;
+          out[row * 128 + col] = dacc[ti][2 * b + tj][v];
+        }
+  }
+  if (tid == 0) A.vflag[item] = 1;
+  double pd = wave_sum(double(pairs));
+  if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
+  });
+}
+
+// FP64 operands: the 4-wave Vxc kernel of k_vgemm_f32 on v_mfma_f64_16x16x4f64 (same items and results as
+// k_vgemm), with 16-point sub-steps so that a ring slot (4 Phi slabs and 4 Z slabs of 32 x 16) stays
+// 32 KB; MFMA step kk takes point 4 (l / 16) + kk of the sub-step.  With `accumulate` set, an item whose
+// partial an earlier launch wrote adds to it (the meta-GGA term).
+__global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
+  typedef Mma<double> M;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  constexpr int kSP = 16, kNS = kG / kSP, kSlab = kD * kSP, kSlot = 8 * kSlab;
+  __shared__ __align__(16) double ring[2 * kSlot];
+  __shared__ int s_m[NTV4];
+  __shared__ int s_ip[NTV4], s_iq[NTV4];
+  __shared__ long long s_bo[NTV4];
+  __shared__ int s_w[4];
+  run_items(A.q, A.item0, [&](int64_t il) {
+  const int64_t item = A.item0 + il;
+  const VItem it = A.items[item];
+  const int tid = threadIdx.x, l = tid & 63;
+  const int ws = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m16 = l & 15, g = l >> 4;
+  const double *Pd = static_cast<const double *>(A.phi) - size_t(A.ret0) * (kD * kG);   // by retained tile
+  const double *Zd = static_cast<const double *>(A.zws) - size_t(A.ret0) * (kD * kG);
+  const int prev = A.accumulate ? A.vflag[item] : 0;
+
+  d4 acc[2][8];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 8; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
+  unsigned long long pairs = 0;
+  int any = 0;
+  for (int base = it.r0; base < it.r1; base += NTV4) {
+    const int r = base + tid;
+    int mask = 0;
+    if (r < it.r1) mask = A.vmask[A.vmoff[r] - A.vm_base + it.lpair];
+    int tot;
+    const int pos = block_scan(mask != 0, s_w, &tot);
+    if (mask) {
+      s_m[pos] = mask;
+      const int64_t cb = A.cioff[r];
+      s_ip[pos] = A.cinfo[cb + it.pc];
+      s_iq[pos] = A.cinfo[cb + it.qc];
+      s_bo[pos] = A.st.blk_off[r];
+      pairs += __popc(mask);
+    }
+    __syncthreads();
+    any |= tot;
+    const int nst = kNS * tot;
+    auto issue = [&](int st) {
+      const int e = st / kNS, sub = st % kNS;
+      const int m = __builtin_amdgcn_readfirstlane(s_m[e]);
+      const long long bo = s_bo[e];
+      double *dst = ring + (st & 1) * kSlot;
+      if ((m >> (4 * ws)) & 15) {
+        const int info = __builtin_amdgcn_readfirstlane(s_ip[e]);
+        const double *src = Pd + size_t(bo + tile_pos(info, ws)) * (kD * kG) + kSP * sub;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          dma16(src + i * kG + 2 * cu, dst + ws * kSlab + 128 * k);
+        }
+      }
+      if ((m >> ws) & 0x1111) {
+        const int info = __builtin_amdgcn_readfirstlane(s_iq[e]);
+        const double *src = Zd + size_t(bo + tile_pos(info, ws)) * (kD * kG) + kSP * sub;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          dma16(src + i * kG + 2 * cu, dst + (4 + ws) * kSlab + 128 * k);
+        }
+      }
+    };
+    if (nst > 0) issue(0);
+    for (int st = 0; st < nst; ++st) {
+      wait_vm_lds<0>();
+      wg_barrier();
+      if (st + 1 < nst) issue(st + 1);
+      const int m = (__builtin_amdgcn_readfirstlane(s_m[st / kNS]) >> (4 * ws)) & 15;
+      if (m) {
+        const double *sl = ring + (st & 1) * kSlot;
+        d2 fa[2][2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh)
+            fa[t][hh] = *reinterpret_cast<const d2 *>(sl + ws * kSlab + (16 * t + m16) * kSP +
+                                                      2 * ((2 * g + hh) ^ (m16 & 7)));
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if (!((m >> b) & 1)) continue;
+          d2 fb[2][2];
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+              fb[t][hh] = *reinterpret_cast<const d2 *>(sl + (4 + b) * kSlab + (16 * t + m16) * kSP +
+                                                        2 * ((2 * g + hh) ^ (m16 & 7)));
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+              for (int tj = 0; tj < 2; ++tj)
+                acc[ti][2 * b + tj] = M::mma(fa[ti][kk >> 1][kk & 1], fb[tj][kk >> 1][kk & 1], acc[ti][2 * b + tj]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!any) {
+    if (tid == 0 && !A.accumulate) A.vflag[item] = 0;
+    return;
+  }
+  double *out = A.vpart + size_t(item) * (128 * 128);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 8; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 32 * ws + 16 * ti + M::row(v, l), col = 16 * tj + m16;
+        const double val = acc[ti][tj][v];
+        out[row * 128 + col] = prev ? out[row * 128 + col] + val : val;
+      }
+  if (tid == 0) A.vflag[item] = 1;
+  double pd = wave_sum(double(pairs));
+  if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
+  });
+}
+
 // One workgroup row per chunk pair (all molecules): FP64 sum of its segment partials in segment order.
 // FP32 plans: the diagonal tiles M_pp of the Vxc product in FP64.  One workgroup per Vxc item of a
 // diagonal chunk pair (pc = qc); wave w owns the tile p = 4 pc + w and walks the segment's blocks whose
@@ -1589,6 +2051,11 @@ void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
         k_xgemm_f32<true><<<gx, NTX4, 0, s>>>(xa);
       else
         k_xgemm_f32<false><<<gx, NTX4, 0, s>>>(xa);
+    } else if constexpr (sizeof(T) == 8) {
+      if (P.gga)
+        k_xgemm_f64<true><<<gx, NTX4, 0, s>>>(xa);
+      else
+        k_xgemm_f64<false><<<gx, NTX4, 0, s>>>(xa);
     } else {
       if (P.gga)
         k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(xa);
@@ -1606,7 +2073,7 @@ void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
         for (int a = 0; a < 3; ++a) {
           k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr);
           ta.part = E.tpart[a];
-          k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(ta);
+          k_xgemm_f64<true><<<gx, NTX4, 0, s>>>(ta);
         }
       }
     }
@@ -1730,7 +2197,12 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
         if (e == hipSuccess) e = hipStreamWaitEvent(P.side_stream, P.fork_ev, 0);
         if (e != hipSuccess) return e;
       }
-      if (nvit > 0) k_vgemm<T><<<gv, NTV, 0, s>>>(va);
+      if (nvit > 0) {
+        if constexpr (sizeof(T) == 4)
+          k_vgemm_f32<<<gv, NTV4, 0, s>>>(va);
+        else
+          k_vgemm_f64<<<gv, NTV4, 0, s>>>(va);
+      }
       if constexpr (sizeof(T) == 8 && NPC == 0) {
         if (is_mgga_xc(P.opts.xc) && nvit > 0 && nret > 0) {
           // meta-GGA: + sum_a d_a Phi (w v_tau / 4 d_a Phi)^T over every pair of retained tiles of a block
@@ -1744,7 +2216,7 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
           for (int a = 0; a < 3; ++a) {
             k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr);
             k_tscale<<<nret, kG, 0, s>>>(P.st, C.ret0, E.ctau, E.tdphi, E.tB);
-            k_vgemm<T><<<gv, NTV, 0, s>>>(tv);
+            k_vgemm_f64<<<gv, NTV4, 0, s>>>(tv);
           }
         }
       }
@@ -1906,7 +2378,7 @@ hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
     const int64_t gv = 8 * P.vq.maxlen_h[ci];
     auto product = [&](const void *opA, const void *opB, int skip_diag, int mode, int slot) {
       k_gmask<<<nblk, NT, 0, s>>>(m_args(P, ci), E.amax, skip_diag);
-      k_vgemm<double><<<gv, NTV, 0, s>>>(v_args(P, ci, opA, opB));
+      k_vgemm_f64<<<gv, NTV4, 0, s>>>(v_args(P, ci, opA, opB));
       k_gcontract<<<nvit, kG, 0, s>>>(P.items, C.vit0, P.st.mol, P.pair_info, E.vflag, E.vpart, Dt, mode, slot,
                                       P.grad_ws.gitem);
     };
