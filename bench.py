@@ -83,6 +83,36 @@ def time_path(plan, D, steps, warmup, torch):
     return ms, stage, st, float(exc.item()), vxc.cpu().numpy(), rho
 
 
+UNIT_FLOP = 2.0 * 32 * 32 * 128   # one executed (p, q, r) tile triple
+GEMM_KERNELS = {"fp32": ("k_xgemm_f32", "k_vgemm_f32"), "fp64": ("k_xgemm_f64", "k_vgemm_f64"),
+                "bf16x6": ("k_xgemm_bf16", "k_vgemm_f32"), "bf16x3": ("k_xgemm_bf16", "k_vgemm_f32")}
+
+
+def gemm_rooflines(prec, stats, stage):
+    """Rates of the two block-GEMM kernels from the stage events of one plan (one grid chunk): X = D Phi is
+    the whole xgemm stage; the Vxc stage also holds the pair-mask kernel and, for FP32 operands, the FP64
+    diagonal kernel on a side stream, so its rate is a lower bound of the Vxc kernel's.  Work of FP32 plans'
+    diagonal triples (FP64 MFMA) is counted apart."""
+    kx, kv = GEMM_KERNELS[prec]
+    peak = PEAK_TFLOPS["fp64" if prec == "fp64" else "fp32"]
+    diag = stats.get("n_pairs_v_diag", 0)
+    fx, fv, fd = UNIT_FLOP * stats["n_pairs_x"], UNIT_FLOP * (stats["n_pairs_v"] - diag), UNIT_FLOP * diag
+    tx, tv = stage["xgemm"] * 1e-3, stage["vgemm"] * 1e-3
+    out = {"x": {"kernel": kx, "tflop": round(fx / 1e12, 4), "ms": round(stage["xgemm"], 4),
+                 "tflops": round(fx / tx / 1e12, 3), "frac": round(fx / tx / 1e12 / peak, 4)},
+           "v": {"kernel": kv + (" (stage also holds k_vmask and the concurrent k_vdiag)" if diag else
+                                 " (stage also holds k_vmask)"),
+                 "tflop": round(fv / 1e12, 4), "ms": round(stage["vgemm"], 4),
+                 "tflops": round(fv / tv / 1e12, 3), "frac": round(fv / tv / 1e12 / peak, 4)},
+           "combined": {"tflops": round((fx + fv) / (tx + tv) / 1e12, 3),
+                        "frac": round((fx + fv) / (tx + tv) / 1e12 / peak, 4)},
+           "peak_tflops": peak}
+    if diag:
+        out["v_diag_fp64"] = {"kernel": "k_vdiag", "tflop": round(fd / 1e12, 4), "n_triples": diag,
+                              "peak_tflops": PEAK_TFLOPS["fp64"]}
+    return out
+
+
 def cpu_baseline(p, n_sample=300000, seed=0):
     """The FP64 oracle (dense, NumPy + host BLAS) on a random sample of grid points, scaled to one
     full evaluation (its cost is linear in the number of points)."""
@@ -240,7 +270,7 @@ def bench_batch(args, torch):
     # a replayed graph records no stage events: the GEMM work of the whole evaluation over its time (a lower
     # bound of the rate of the two block-GEMM kernels)
     achieved = flops / (mix["ms"] * 1e-3) / 1e12
-    out["roofline"] = {"bound": "mfma", "kernel": "k_xgemm + k_vgemm (captured graph: whole evaluation)",
+    out["roofline"] = {"bound": "mfma", "kernel": "k_xgemm_f32 + k_vgemm_f32 (captured graph: whole evaluation)",
                        "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
                        "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": None}
     if not args.no_cpu_baseline:
@@ -354,13 +384,12 @@ def bench_learned(args, torch):
     # roofline of the dominant block-GEMM kernel of the run with the network (as for the single-molecule
     # line; with several grid chunks the combined stage and the GEMM work of the whole evaluation)
     if m["chunks"] > 1:
-        kernel = "k_xgemm + k_vgemm (%d grid chunks: combined stage)" % m["chunks"]
+        kernel = "k_xgemm_f32 + k_vgemm_f32 (%d grid chunks: combined stage)" % m["chunks"]
         achieved = m["st"]["gemm_flops"] / (m["stage"]["vgemm"] * 1e-3) / 1e12
     else:
         dom = "xgemm" if m["stage"]["xgemm"] >= m["stage"]["vgemm"] else "vgemm"
-        kernel = "k_" + dom
-        pairs = m["st"]["n_pairs_x"] if dom == "xgemm" else m["st"]["n_pairs_v"]
-        achieved = 2.0 * 32 * 32 * 128 * pairs / (m["stage"][dom] * 1e-3) / 1e12
+        g = gemm_rooflines("fp32", m["st"], m["stage"])["x" if dom == "xgemm" else "v"]
+        kernel, achieved = g["kernel"], g["tflops"]
     out["roofline"] = {"bound": "mfma", "kernel": kernel, "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32"],
                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": None}
     print(json.dumps(out), flush=True)
@@ -381,6 +410,8 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="threshold sweep t_b = t_d on workload 1 (retained fraction, time, errors) instead of the bench")
     ap.add_argument("--no-dense", action="store_true", help="skip the unscreened (t_b = t_d = 0) GPU comparator")
+    ap.add_argument("--no-other-order", action="store_true",
+                    help="workload 1: skip the timing of the other basis order (for profiler runs)")
     ap.add_argument("--ao-order", default="overlap", choices=["overlap", "atom"],
                     help="basis order of the timed plans on workloads 1 and 2: overlap-signature clustering (the "
                          "paper's reordering; default) or atom order; workload 1 also times the other order once")
@@ -478,10 +509,14 @@ def main():
         "cold_ms": round(mix["cold_ms"], 1),
         "electrons": mix["elec"], "n_occ": p.n_occ,
     }
+    if mix["info"]["n_grid_chunks"] == 1:
+        out["gemms"] = gemm_rooflines(forms[0], mix["stats"], mix["stage"])
     if "fp64" in res:
         f64 = res["fp64"]
         out["fp64"] = {"ms": round(f64["ms"], 4), "tflops": round(f64["stats"]["gemm_flops"] / (f64["ms"] * 1e-3) / 1e12, 3),
                        "stage_ms": {k: round(v, 4) for k, v in f64["stage"].items()}}
+        if f64["info"]["n_grid_chunks"] == 1:
+            out["fp64"]["gemms"] = gemm_rooflines("fp64", f64["stats"], f64["stage"])
         out["speedup_mixed_vs_fp64"] = round(f64["ms"] / mix["ms"], 3)
         out["err_mixed_vs_fp64"] = {"E_xc": abs(mix["E"] - f64["E"]), "V_maxabs": float(np.abs(mix["V"] - f64["V"]).max())}
     out["precision_forms"] = {}
@@ -520,7 +555,7 @@ def main():
         plan.close()
         del rho
         torch.cuda.empty_cache()
-    if args.config == 1:
+    if args.config == 1 and not args.no_other_order:
         other = "atom order" if so is not None else "overlap-signature clustering"
         so2 = None
         if so is None:
@@ -548,13 +583,13 @@ def main():
     traffic = None
     if mix["info"]["n_grid_chunks"] > 1:
         achieved = flops / (mix["stage"]["vgemm"] * 1e-3) / 1e12
-        kernel = "k_xgemm + k_vgemm (%d grid chunks: combined stage, all kernels between D preparation and "\
-                 "the final sums)" % mix["info"]["n_grid_chunks"]
+        kernel = "%s + %s (%d grid chunks: combined stage, all kernels between D preparation and "\
+                 "the final sums)" % (GEMM_KERNELS[forms[0]] + (mix["info"]["n_grid_chunks"],))
     else:
         dom = "xgemm" if mix["stage"]["xgemm"] >= mix["stage"]["vgemm"] else "vgemm"
-        pairs = mix["stats"]["n_pairs_x"] if dom == "xgemm" else mix["stats"]["n_pairs_v"]
-        achieved = 2.0 * 32 * 32 * 128 * pairs / (mix["stage"][dom] * 1e-3) / 1e12
-        kernel = "k_" + dom
+        g = out["gemms"]["x" if dom == "xgemm" else "v"]
+        achieved = g["tflops"]
+        kernel = g["kernel"]
         # the counters in TRAFFIC were taken on the 200-atom chain (workload 1) from these exact sources
         if args.config == 1 and os.path.exists(TRAFFIC):
             t = json.load(open(TRAFFIC))

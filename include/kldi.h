@@ -168,6 +168,9 @@ typedef struct {
   double gemm_flops;                   /* 2 d^2 G (n_pairs_x + n_pairs_v): algorithmic GEMM work  */
   int32_t nonfinite_d;                 /* 1 if D held a NaN or Inf                                */
   int64_t n_points_mlp;                /* grid points evaluated by an attached functional surrogate */
+  int64_t n_pairs_v_diag;              /* of n_pairs_v, the diagonal triples (p, p, r) that an FP32
+                                          plan runs on FP64 MFMA (0 for FP64 plans, whose Vxc product
+                                          is FP64 throughout)                                         */
 } kldi_eval_stats_t;
 
 /* Stages of one evaluation, for kldi_eval_timing. */

@@ -130,7 +130,7 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
 
     # M = Phi Z^T over executable grid blocks
     M = np.zeros((nao, nao))
-    nP_M = 0
+    nP_M = nP_M_diag = 0
     for p, (a0, a1) in enumerate(T):
         for q, (c0, c1) in enumerate(T):
             if not gga and q < p:
@@ -139,6 +139,8 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
                              for r in range(nB)])
             n_exec, E_M = addressing.parallel_where(mask)
             nP_M += sum(wt[r] for r in E_M)
+            if p == q:
+                nP_M_diag += sum(wt[r] for r in E_M)
             acc = np.zeros((a1 - a0, c1 - c0))
             for r in E_M:
                 g0, g1 = B[r]
@@ -174,7 +176,7 @@ def eval_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_
     grad_c[:, pt_perm] = grad
     V = np.empty((nao, nao))
     V[np.ix_(ao_perm, ao_perm)] = Vp
-    return dict(rho=rho_c, grad=grad_c, E=E, V=V, S_phi=S_phi, S_D=S_D, b=b, s=s, a=a, z=z, nP_X=nP_X, nP_M=nP_M,
+    return dict(rho=rho_c, grad=grad_c, E=E, V=V, S_phi=S_phi, S_D=S_D, b=b, s=s, a=a, z=z, nP_X=nP_X, nP_M=nP_M, nP_M_diag=nP_M_diag,
                 ao_perm=ao_perm, pt_perm=pt_perm, n_tiles=nT, n_blocks=nB)
 
 
@@ -225,7 +227,7 @@ def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e
         m_ji = np.zeros(len(ve))
     rho = np.zeros(npt)
     ef = np.zeros(npt)
-    nP_X = nP_M = 0
+    nP_X = nP_M = nP_M_diag = 0
     for c0b in range(0, len(B), blocks_per_chunk):
         blocks = B[c0b:c0b + blocks_per_chunk]
         g0c, g1c = blocks[0][0], blocks[-1][1]
@@ -272,6 +274,7 @@ def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e
             if not gga:
                 exm &= R[:, None] <= R[None, :]
             nP_M += int(exm.sum()) * wt
+            nP_M_diag += int(np.trace(exm)) * wt
             if v_entries is None:
                 Mr = np.where(exm[np.ix_(tr, tr)], phr @ Z.T, 0.0)
                 M[np.ix_(rows, rows)] += Mr
@@ -288,7 +291,7 @@ def eval_blocked_stream(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e
     E = math.fsum(ef.tolist())
     rho_c = np.empty(npt)
     rho_c[pt_perm] = rho
-    out = dict(rho=rho_c, E=E, nP_X=nP_X, nP_M=nP_M, ao_perm=ao_perm, pt_perm=pt_perm)
+    out = dict(rho=rho_c, E=E, nP_X=nP_X, nP_M=nP_M, nP_M_diag=nP_M_diag, ao_perm=ao_perm, pt_perm=pt_perm)
     if v_entries is None:
         if gga:
             Vp = M + M.T

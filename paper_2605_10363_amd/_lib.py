@@ -64,7 +64,8 @@ class kldi_tune_t(ctypes.Structure):
 
 class kldi_eval_stats_t(ctypes.Structure):
     _fields_ = [("n_pairs_x", ctypes.c_int64), ("n_pairs_v", ctypes.c_int64), ("gemm_flops", ctypes.c_double),
-                ("nonfinite_d", ctypes.c_int32), ("n_points_mlp", ctypes.c_int64)]
+                ("nonfinite_d", ctypes.c_int32), ("n_points_mlp", ctypes.c_int64),
+                ("n_pairs_v_diag", ctypes.c_int64)]
 
 
 class kldi_mlp_cfg(ctypes.Structure):

@@ -12,14 +12,7 @@ namespace kldi {
 namespace dev {
 
 constexpr int NT = 256;          // threads per workgroup (4 waves of 64)
-// LDS row strides (elements).  gfx950 serves a 32-bit LDS read of a wave as two 32-lane halves over
-// 32 banks (measured); 64-bit reads in groups of 16 lanes.  An MFMA fragment read of a [row][k] tile has
-// lanes (row = l % 16, k = l / 16): conflict-free when 2 rows are one bank apart for FP32 (stride 34,
-// 2 * row + k covers the 32 banks of a half) and for FP64 an odd stride; a [k][col] tile read by
-// (k = l / 16, col = l % 16) needs a stride of 16 mod 32 banks for FP32 (144).
-template <class T> constexpr int lda_s() { return sizeof(T) == 4 ? 34 : 33; }   // 32-wide row tiles
-template <class T> constexpr int ldb_s() { return sizeof(T) == 4 ? 144 : 130; } // 128-wide rows
-constexpr int kMaxNp = 512;      // retained tiles per grid block handled by k_xgemm
+constexpr int kMaxNp = 512;      // retained tiles per grid block handled by the X kernels
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));

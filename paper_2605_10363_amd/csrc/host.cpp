@@ -1266,7 +1266,7 @@ kldi_status kldi_eval_check(kldi_plan *plan, kldi_eval_stats_t *out, void *strea
     kldi::set_error("plan and out must not be NULL");
     return KLDI_E_ARG;
   }
-  unsigned long long c[4] = {0, 0, 0, 0};
+  unsigned long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   kldi_status st = kldi::guarded([&] {
     kldi::check_hip(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "sync");
     kldi::check_hip(hipMemcpy(c, plan->impl.ev.counters, sizeof(c), hipMemcpyDeviceToHost), "copy counters");
@@ -1276,6 +1276,7 @@ kldi_status kldi_eval_check(kldi_plan *plan, kldi_eval_stats_t *out, void *strea
   out->n_pairs_v = int64_t(c[1]);
   out->gemm_flops = 2.0 * kldi::kD * kldi::kD * kldi::kG * double(c[0] + c[1]);
   out->n_points_mlp = int64_t(c[3]);
+  out->n_pairs_v_diag = int64_t(c[6]);
   out->nonfinite_d = c[2] ? 1 : 0;
   if (c[2]) {
     kldi::set_error("D holds a non-finite entry");
@@ -1465,6 +1466,6 @@ kldi_status kldi_xc_eval(int32_t xc, const double *rho_dev, const double *sigma_
 
 const char *kldi_last_error(void) { return kldi::g_last_error.c_str(); }
 
-int32_t kldi_version(void) { return 3; }
+int32_t kldi_version(void) { return 4; }
 
 }  // extern "C"

@@ -9,14 +9,16 @@
 //   k_dprep    D (caller order, FP64) -> internal AO order, 32x32 tiles, working precision; block
 //              summaries a_pq = max|D_pq| (eq. block_summary_A); non-finite check
 //   k_basis    Phi on the retained (tile, grid block) pairs only (eq. phi_def)
-//   k_xgemm    one workgroup per (grid block r, chunk of 4 output tiles p of S_r): the executable q
+//   k_xgemm_*  one workgroup per (grid block r, chunk of 4 output tiles p of S_r): the executable q
 //              are selected by a_pq * b_qr >= t_d (eq. block_pair_filter) and compacted by prefix
 //              sum (Appendix D); X_pr = sum_q D_pq Phi_qr on MFMA with LDS-staged tiles, accumulated
 //              in registers before the epilogue (Sec. III-C.2); the chunk's rho / grad rho partials
+//              (_f32 / _f64: FP32 / FP64 operands, 4 waves; _bf16: BF16 split operands, 8 waves)
 //   k_xfunc    one workgroup per grid block: fixed-order FP64 rho, the functional, E_xc partial
 //   k_zform    Z on every retained tile with its max-abs summary
-//   k_vgemm    one workgroup per (row chunk, column chunk, segment of grid blocks): executable grid
+//   k_vgemm_*  one workgroup per (row chunk, column chunk, segment of grid blocks): executable grid
 //              blocks selected by b_pr * z_qr >= t_d and compacted; M_pq = sum_r Phi_pr Z_qr^T on MFMA
+//              (_f32 / _f64: FP32 / FP64 operands, 4 waves)
 //   k_vreduce  FP64 sum of the segment partials in fixed order
 //   k_vsym     Vxc = M + M^T (GGA) or mirrored 2M (LDA), back to the caller's AO order
 //   k_esum     E_xc of each molecule as a fixed-order FP64 sum of its per-block partials
@@ -237,18 +239,6 @@ __global__ __launch_bounds__(kG) void k_basis(BasisDev B, GridDev g, StructDev s
 }
 
 // 16-byte unit copies between global memory and LDS rows
-template <class T>
-struct Units {
-  static constexpr int E = 16 / sizeof(T);  // elements per 16-byte unit
-};
-
-template <class T>
-__device__ __forceinline__ void lds_store_unit(T *dst, const uint4 &u) {
-  const T *src = reinterpret_cast<const T *>(&u);
-#pragma unroll
-  for (int m = 0; m < Units<T>::E; ++m) dst[m] = src[m];
-}
-
 // Global -> LDS copies that bypass registers (global_load_lds_dwordx4): lane l of the wave writes its
 // 16 bytes at lds_wave + 16 l (measured on gfx950); lds_wave must be the same for the whole wave (it
 // goes to M0).  The copies count in vmcnt like vector loads, in issue order; the GEMM loops wait for
@@ -313,32 +303,25 @@ struct XArgs {
   QArgs q;
 };
 
-constexpr int NTX = 512;   // threads per X workgroup: 8 waves, each 32 rows x 64 points
+constexpr int NTX = 512;   // threads per BF16 X workgroup: 8 waves, each 32 rows x 64 points
 
 
-// One workgroup per (grid block r, chunk c of 4 retained output tiles): X_pr = sum_q D_pq Phi_qr for
-// the 4 tiles p = S_r[4c .. 4c+3], then the chunk's contribution to rho and grad rho.  Wave w owns
-// tile 4c + (w & 3) and points 64 (w >> 2) .. 64 (w >> 2) + 63.
-// FP32 operands: MFMA accumulation spans one 32-AO K tile, the running sum is FP64.
-// NPC > 0 (T = float): the operands are NPC BF16 pieces each, on BF16 MFMA (Dt holds D's pieces, phix
-// Phi's); the FP32 Phi serves the epilogue.
-template <class T, bool GGA, int NPC>
-__global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
-  typedef Mma<T> M;
+// BF16 split plans: one workgroup per (grid block r, chunk c of 4 retained output tiles): X_pr =
+// sum_q D_pq Phi_qr for the 4 tiles p = S_r[4c .. 4c+3], then the chunk's contribution to rho and grad rho.
+// Wave w owns tile 4c + (w & 3) and points 64 (w >> 2) .. 64 (w >> 2) + 63.  The operands are NPC BF16
+// pieces each, on BF16 MFMA (Dt holds D's pieces, phix Phi's), accumulated in FP32 per K tile and in
+// FP64 beyond; the FP32 Phi serves the epilogue.
+template <bool GGA, int NPC>
+__global__ __launch_bounds__(NTX, 2) void k_xgemm_bf16(XArgs A) {
+  typedef Mma<float> M;
   typedef typename M::acc_t acc_t;
-  constexpr int E = Units<T>::E;
-  constexpr bool F32 = sizeof(T) == 4;
-  // FP32: a ring of kRing LDS slots of one K step each; a step takes kPer compacted entries, each 4 D
-  // tiles + one Phi tile (32 KB).  FP64: one padded stage filled through registers.
-  constexpr int kRing = 2, kPer = 2, kEntF = 4 * kD * kD + kD * kG, kSlotF = kPer * kEntF;
-  constexpr int LDA_S = lda_s<T>(), LDB_S = ldb_s<T>();
-  constexpr int kA = 128 * LDA_S, kB = 32 * LDB_S;
+  typedef float T;
   constexpr int kXsBytes = 4 * kD * kG * 8;   // the epilogue's X (FP64, 4 tiles) overlays the staging area
-  constexpr int kStageBytes = std::max(F32 ? kRing * kSlotF * 4 : (kA + kB) * int(sizeof(T)), kXsBytes);
+  constexpr int kStageBytes = kXsBytes;
   __shared__ __align__(16) unsigned char s_raw[kStageBytes];
   __shared__ int s_p[kMaxNp];
   __shared__ int s_list[kMaxNp];
-  __shared__ int s_q[kMaxNp];      // q of each compacted entry (FP32 path)
+  __shared__ int s_q[kMaxNp];      // q of each compacted entry
   __shared__ int s_w[8];
   __shared__ double s_acc[4][4][kG];
   run_items(A.q, A.item0, [&](int64_t il) {
@@ -350,12 +333,9 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
   const MolDev mo = A.st.mol[A.st.blk_mol[r]];
   const int64_t k0 = A.st.blk_off[r];
   const int np = int(A.st.blk_off[r + 1] - k0);
-  const T *Dt = static_cast<const T *>(A.Dt);
   const T *phi = static_cast<const T *>(A.phi) - size_t(A.ret0) * (kD * kG);   // indexed by retained tile
   // (p, q) tile pair of the molecule -> its position in Dt / amax
   auto dtile = [&](int p, int q) { return size_t(mo.dt0) + size_t(p - mo.tile0) * mo.nt + (q - mo.tile0); };
-  T *sA = reinterpret_cast<T *>(s_raw);                 // FP64: [kA] D tiles, then [kB] Phi
-  T *sB = sA + kA;
   double *Xs = reinterpret_cast<double *>(s_raw);        // [4][32][kG] in the epilogue
 
   for (int t = tid; t < np; t += NTX) s_p[t] = A.st.ret_p[k0 + t];
@@ -410,7 +390,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
       for (int v = 0; v < 4; ++v) dacc[ti][tj][v] = 0.0;
     }
   const bool has_u = 4 * c + u < np;
-  if constexpr (NPC > 0) {
+  {
     // ---- BF16 pieces.  Slot e % 2 holds entry e of the compacted list: the NPC pieces of the 4 D
     // tiles (p_u, q), each [row i][k], then the NPC pieces of Phi_q, each [point][k]; a row is 64
     // bytes, 4 units of 16 bytes, unit c of row i stored at c ^ ((i >> 1) & 3) (the 8 rows a
@@ -493,170 +473,6 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
       }
     }
     __syncthreads();
-  } else if constexpr (F32) {
-    // ---- FP32 operands.  Slot S % kRing holds K step S: entries kPer S .. kPer S + kPer - 1 of the
-    // compacted list, each the 4 D tiles (p_u, q) as [row i][k] with the 16-byte units of row i
-    // XOR-swizzled (unit c at c ^ (i & 7)), then Phi_q as [k][point].  The copies go global -> LDS
-    // directly, one step ahead; one barrier per step.  Index maps of the MFMA steps: step kk of a wave
-    // takes k = 8 (l / 16) + kk, so a lane reads the 8 values of its row of D with two 16-byte loads,
-    // and output column c of sub-tile tj is point 64 h + 4 c + tj, so a lane reads its 4 values of a
-    // row of Phi_q with one 16-byte load.
-    float *ring = reinterpret_cast<float *>(s_raw);
-    const int ws = __builtin_amdgcn_readfirstlane(w), us = ws & 3;
-    const int m16 = l & 15, g = l >> 4;
-    const float *Df = reinterpret_cast<const float *>(Dt);
-    const float *Pf = reinterpret_cast<const float *>(phi);
-    // D tile row of this wave's chunk entry (waves 0-3): an entry past the end of S_r uses entry np - 1
-    // (valid memory, never multiplied: its wave has no executable pair)
-    const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + (ws & 3), np - 1)]);
-    const float *Drow = Df + dtile(pa, mo.tile0) * (kD * kD);
-    const int n_step = (n_list + kPer - 1) / kPer;
-    // every wave copies 4 KB of each entry of step S (the entries past the list's end repeat its last
-    // entry, so every step issues 4 kPer copies per wave)
-    auto issue = [&](int S) {
-#pragma unroll
-      for (int j = 0; j < kPer; ++j) {
-        const int e = min(kPer * S + j, n_list - 1);
-        float *dst = ring + (S & (kRing - 1)) * kSlotF + j * kEntF + ws * 1024;
-        if (ws < 4) {
-          const int q = __builtin_amdgcn_readfirstlane(s_q[e]);
-          const float *src = Drow + size_t(q - mo.tile0) * (kD * kD);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
-            dma16(src + i * kD + 4 * cu, dst + 256 * m);
-          }
-        } else {
-          const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
-          const float *src = Pf + size_t(k0 + t) * (kD * kG) + 1024 * (ws - 4);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) dma16(src + 4 * (64 * m + l), dst + 256 * m);
-        }
-      }
-    };
-    struct Frag {
-      f4 a[2][2];   // rows 16 ti + l % 16 of tile u, k = 8 (l / 16) + 4 hh .. + 3
-      f4 b[8];      // row k = 8 (l / 16) + kk of Phi_q, points 64 h + 4 (l % 16) .. + 3
-    };
-    auto frag = [&](const float *se, Frag &F) {
-#pragma unroll
-      for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
-          F.a[ti][hh] = *reinterpret_cast<const f4 *>(se + us * (kD * kD) + (16 * ti + m16) * kD +
-                                                      4 * ((2 * g + hh) ^ (m16 & 7)));
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk)
-        F.b[kk] = *reinterpret_cast<const f4 *>(se + 4 * kD * kD + (8 * g + kk) * kG + 64 * h + 4 * m16);
-    };
-    // the FP32 accumulators of sub-tile row ti are added to the FP64 sums every 8 MFMA steps (one K
-    // tile), row 0 after step 3 and row 1 after step 7 of each K tile, so the conversion and FP64 adds
-    // of one row overlap the MFMAs of the other.  (Measured at the 200-atom chain: flushing after every
-    // second K tile saves 4% of this kernel but raises the E_xc error sevenfold; flushing the two waves of
-    // a SIMD at different steps changes nothing.)
-    auto flush = [&](int ti) {
-#pragma unroll
-      for (int tj = 0; tj < 4; ++tj) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
-        acc[ti][tj] = acc_t{};
-      }
-    };
-    auto mfma_steps = [&](const Frag &F, int k0s, int k1s) {
-#pragma unroll
-      for (int kk = k0s; kk < k1s; ++kk) {
-        const float a0 = F.a[0][kk >> 2][kk & 3], a1 = F.a[1][kk >> 2][kk & 3];
-#pragma unroll
-        for (int tj = 0; tj < 4; ++tj) {
-          acc[0][tj] = M::mma(a0, F.b[kk][tj], acc[0][tj]);
-          acc[1][tj] = M::mma(a1, F.b[kk][tj], acc[1][tj]);
-        }
-      }
-    };
-    static_assert(kRing == 2, "the waits below assume one step in flight");
-    if (n_step > 0) issue(0);
-    // step S: wait until this wave's copies of step S have landed and its reads of step S - 1 are done;
-    // after the barrier the slot of step S - 1 takes step S + 1.  (Measured: issuing the copies
-    // between MFMA steps, or reading the next step's fragments during this step's MFMAs, is slower.)
-    for (int S = 0; S < n_step; ++S) {
-      wait_vm_lds<0>();
-      wg_barrier();
-      if (S + 1 < n_step) issue(S + 1);
-#pragma unroll
-      for (int j = 0; j < kPer; ++j) {
-        const int e = kPer * S + j;
-        if (e < n_list && ((__builtin_amdgcn_readfirstlane(s_list[e] >> 16) >> us) & 1)) {
-          Frag F;
-          frag(ring + (S & (kRing - 1)) * kSlotF + j * kEntF, F);
-          mfma_steps(F, 0, 4);
-          flush(0);
-          mfma_steps(F, 4, 8);
-          flush(1);
-        }
-      }
-    }
-    __syncthreads();
-  } else {
-    constexpr int UA = (kD * kD) / E;   // 16-byte units per D tile
-    constexpr int UB = (kD * kG) / E;   // units per Phi tile
-    constexpr int NA = 4 * UA / NTX, NB = UB / NTX;
-    uint4 ra[NA], rb[NB];
-    auto fetch = [&](int e) {
-      const int t = s_list[e] & 0xffff;
-      const int q = s_p[t];
-#pragma unroll
-      for (int m = 0; m < NA; ++m) {
-        const int un = tid + NTX * m, ww = un / UA, uu = un % UA;
-        ra[m] = make_uint4(0, 0, 0, 0);
-        if (4 * c + ww < np)
-          ra[m] = reinterpret_cast<const uint4 *>(Dt + dtile(s_p[4 * c + ww], q) * (kD * kD))[uu];
-      }
-      const uint4 *src = reinterpret_cast<const uint4 *>(phi + size_t(k0 + t) * (kD * kG));
-#pragma unroll
-      for (int m = 0; m < NB; ++m) rb[m] = src[tid + NTX * m];
-    };
-    auto stash = [&]() {
-      T *a = sA;
-      T *b = sB;
-#pragma unroll
-      for (int m = 0; m < NA; ++m) {
-        const int un = tid + NTX * m, ww = un / UA, e0 = (un % UA) * E;
-        lds_store_unit<T>(&a[(32 * ww + e0 / kD) * LDA_S + e0 % kD], ra[m]);
-      }
-#pragma unroll
-      for (int m = 0; m < NB; ++m) {
-        const int e0 = (tid + NTX * m) * E;
-        lds_store_unit<T>(&b[(e0 / kG) * LDB_S + e0 % kG], rb[m]);
-      }
-    };
-    if (n_list > 0) {
-      fetch(0);
-      stash();
-    }
-    __syncthreads();
-    for (int e = 0; e < n_list; ++e) {
-      const int mask = s_list[e] >> 16;
-      if (e + 1 < n_list) fetch(e + 1);
-      if ((mask >> u) & 1) {
-        const T *a = sA;
-        const T *b = sB;
-#pragma unroll 2
-        for (int kk = 0; kk < 8; ++kk) {
-          const int kc = 4 * kk + (l >> 4);
-          const T a0 = a[(32 * u + (l & 15)) * LDA_S + kc];
-          const T a1 = a[(32 * u + 16 + (l & 15)) * LDA_S + kc];
-#pragma unroll
-          for (int tj = 0; tj < 4; ++tj) {
-            const T bv = b[kc * LDB_S + 64 * h + 16 * tj + (l & 15)];
-            acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
-            acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
-          }
-        }
-      }
-      __syncthreads();
-      if (e + 1 < n_list) stash();
-      __syncthreads();
-    }
   }
 
   // ---- epilogue: rho_i += sum_mu Phi_mu,i X_mu,i and grad rho_i += 2 sum_mu grad Phi_mu,i X_mu,i over
@@ -672,7 +488,7 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
       for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          Xw[(16 * ti + M::row(v, l)) * kG + 64 * h + ((F32 && NPC == 0) ? 4 * (l & 15) + tj : 16 * tj + (l & 15))] =
+          Xw[(16 * ti + M::row(v, l)) * kG + 64 * h + 16 * tj + (l & 15)] =
               dacc[ti][tj][v] + double(acc[ti][tj][v]);
   }
   __syncthreads();
@@ -721,13 +537,15 @@ __global__ __launch_bounds__(NTX, 2) void k_xgemm(XArgs A) {
 
 constexpr int NTX4 = 256;   // threads per FP32 X workgroup: 4 waves, wave u owns output tile u (32 rows x 128 points)
 
-// FP32 operands: one workgroup of 4 waves per (grid block r, chunk c of 4 retained output tiles), the
-// same items and results as k_xgemm.  Its LDS (78 KB: a two-slot ring of one compacted entry each,
+// FP32 operands: one workgroup of 4 waves per (grid block r, chunk c of 4 retained output tiles p = S_r[4c ..
+// 4c+3]): X_pr = sum_q D_pq Phi_qr over the executable q, then the chunk's contribution to rho and grad rho.
+// Its LDS (78 KB: a two-slot ring of one compacted entry each,
 // 4 D tiles + one Phi tile, which the epilogue's FP64 X of two tiles overlays) lets two workgroups share
 // a CU, so one workgroup's copies, barriers and epilogue overlap the other's MFMAs.  Wave u multiplies
 // D_(p_u, q) (32 x 32) by Phi_qr (32 x 128) on v_mfma_f32_16x16x4f32: MFMA step kk takes k = 8 (l / 16) + kk,
-// output column c of sub-tile tj is point 8 c + tj, so a lane reads its 8 values of a row of Phi_q with
-// two 16-byte loads.  The FP32 accumulators of sub-tile row ti are added to the FP64 sums once per 32
+// output column c of sub-tile tj is point 64 (tj / 4) + 4 c + tj % 4, so a lane reads its 8 values of a
+// row of Phi_q with two 16-byte loads and the 16 lanes of a row read 256 contiguous bytes per load (no
+// bank conflicts; 8 contiguous points per lane made every Phi read a two-way conflict).  The FP32 accumulators of sub-tile row ti are added to the FP64 sums once per 32
 // values of k (row 0 after step 3, row 1 after step 7 of each entry, so the two rows' flushes alternate
 // with MFMAs).
 template <bool GGA>
@@ -842,11 +660,11 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
         for (int hh = 0; hh < 2; ++hh)
           a[ti][hh] = *reinterpret_cast<const f4 *>(se + ws * (kD * kD) + (16 * ti + m16) * kD +
                                                     4 * ((2 * g + hh) ^ (m16 & 7)));
-      const float *sb = se + 4 * kD * kD + 8 * m16;
+      const float *sb = se + 4 * kD * kD + 4 * m16;
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
         const f4 b0 = *reinterpret_cast<const f4 *>(sb + (8 * g + kk) * kG);
-        const f4 b1 = *reinterpret_cast<const f4 *>(sb + (8 * g + kk) * kG + 4);
+        const f4 b1 = *reinterpret_cast<const f4 *>(sb + (8 * g + kk) * kG + 64);
         const float a0 = a[0][kk >> 2][kk & 3], a1 = a[1][kk >> 2][kk & 3];
 #pragma unroll
         for (int tj = 0; tj < 8; ++tj) {
@@ -878,7 +696,8 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
         for (int tj = 0; tj < 8; ++tj)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            Xw[(16 * ti + M::row(v, l)) * kG + 8 * m16 + tj] = dacc[ti][tj][v] + double(acc[ti][tj][v]);
+            Xw[(16 * ti + M::row(v, l)) * kG + 64 * (tj >> 2) + 4 * m16 + (tj & 3)] =
+                dacc[ti][tj][v] + double(acc[ti][tj][v]);
     }
     __syncthreads();
     const int slot = 4 * c + 2 * R + slot_w;
@@ -922,11 +741,11 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
   });
 }
 
-// FP64 operands: the 4-wave X kernel of k_xgemm_f32 on v_mfma_f64_16x16x4f64, the same items and results
-// as k_xgemm.  An FP64 entry (64 KB) is taken in two K halves of 16 values, each a ring slot of 32 KB
+// FP64 operands: the 4-wave X kernel of k_xgemm_f32 on v_mfma_f64_16x16x4f64 (same items).  An FP64 entry (64 KB) is taken in two K halves of 16 values, each a ring slot of 32 KB
 // (4 D half-tiles [row i][k] with the 16-byte units of row i XOR-swizzled, unit c at c ^ (i & 7), and
-// half of Phi_q as [k][point]); MFMA step kk of a half takes k = 4 (l / 16) + kk.  The accumulators are
-// FP64, so X needs no flush.
+// half of Phi_q as [k][point]); MFMA step kk of a half takes k = 4 (l / 16) + kk, and output column c of
+// sub-tile tj is point 32 (tj / 2) + 2 c + tj % 2 (the 16 lanes of a row read 256 contiguous bytes per
+// 16-byte load).  The accumulators are FP64, so X needs no flush.
 template <bool GGA>
 __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f64(XArgs A) {
   typedef Mma<double> M;
@@ -1023,12 +842,12 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f64(XArgs A) {
         for (int hh = 0; hh < 2; ++hh)
           a[ti][hh] = *reinterpret_cast<const d2 *>(se + ws * (kD * kHalf) + (16 * ti + m16) * kHalf +
                                                     2 * ((2 * g + hh) ^ (m16 & 7)));
-      const double *sb = se + 4 * kD * kHalf + 8 * m16;
+      const double *sb = se + 4 * kD * kHalf + 2 * m16;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         d2 b[4];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) b[jj] = *reinterpret_cast<const d2 *>(sb + (4 * g + kk) * kG + 2 * jj);
+        for (int jj = 0; jj < 4; ++jj) b[jj] = *reinterpret_cast<const d2 *>(sb + (4 * g + kk) * kG + 32 * jj);
         const double a0 = a[0][kk >> 1][kk & 1], a1 = a[1][kk >> 1][kk & 1];
 #pragma unroll
         for (int tj = 0; tj < 8; ++tj) {
@@ -1054,7 +873,8 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f64(XArgs A) {
 #pragma unroll
         for (int tj = 0; tj < 8; ++tj)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Xw[(16 * ti + M::row(v, l)) * kG + 8 * m16 + tj] = acc[ti][tj][v];
+          for (int v = 0; v < 4; ++v)
+            Xw[(16 * ti + M::row(v, l)) * kG + 32 * (tj >> 1) + 2 * m16 + (tj & 1)] = acc[ti][tj][v];
     }
     __syncthreads();
     const int slot = 4 * c + 2 * R + slot_w;
@@ -1265,274 +1085,10 @@ struct VArgs {
 };
 
 
-constexpr int NTV = 512;   // threads per Vxc workgroup: 8 waves, each 32 rows x 64 columns
-
-// One workgroup per (row chunk pc, column chunk qc, segment of grid blocks): M_pq = sum_r Phi_pr Z_qr^T
-// over the executable grid blocks of the segment, compacted by prefix sum.  Wave w owns AO tile
-// 4pc + (w & 3) (32 rows) and the two column tiles 4qc + 2(w >> 2) + {0, 1}.
-template <class T>
-__global__ __launch_bounds__(NTV, 2) void k_vgemm(VArgs A) {
-  typedef Mma<T> M;
-  typedef typename M::acc_t acc_t;
-  constexpr int E = Units<T>::E;
-  constexpr int LDA_S = lda_s<T>();
-  constexpr int kS = 128 * LDA_S;  // one A or B stage (4 tiles x 32 rows x 32 points)
-  // FP32 operands: M = Phi Z^T on FP32 MFMA, accumulators flushed to FP64 after every 32-point
-  // sub-step.  The diagonal tiles p = q are left to k_vdiag (FP64): they hold the large same-sign sums w v Phi_mu^2
-  // whose FP32 rounding, correlated over the points of one radial shell where Phi takes one value,
-  // would dominate the error of the mixed path.
-  constexpr bool F32 = sizeof(T) == 4;
-  // FP32: a ring of kRing LDS slots, one kSP-point sub-step each (4 Phi slabs + 4 Z slabs of 32 x kSP,
-  // 64 KB).  FP64: two padded stages filled through registers.
-  constexpr int kRing = 2, kSP = 64, kNS = kG / kSP, kSlab = kD * kSP, kSlotF = 8 * kSlab;
-  constexpr int kStageBytes = F32 ? kRing * kSlotF * 4 : 4 * kS * int(sizeof(T));
-  __shared__ __align__(16) unsigned char s_raw[kStageBytes];
-  T *sA = reinterpret_cast<T *>(s_raw);    // FP64: [2][kS]
-  T *sB = sA + 2 * kS;                     // FP64: [2][kS]
-  __shared__ int s_m[NTV];
-  __shared__ int s_ip[NTV], s_iq[NTV];
-  __shared__ long long s_bo[NTV];
-  __shared__ int s_w[8];
-  run_items(A.q, A.item0, [&](int64_t il) {
-  const int64_t item = A.item0 + il;
-  const VItem it = A.items[item];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int u = w & 3, h = w >> 2;
-  const T *phi = static_cast<const T *>(A.phi) - size_t(A.ret0) * (kD * kG);   // indexed by retained tile
-  const T *zws = static_cast<const T *>(A.zws) - size_t(A.ret0) * (kD * kG);
-  const int prev = A.accumulate ? A.vflag[item] : 0;
-
-  acc_t acc[2][4];
-  double dacc[2][4][4];
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 4; ++tj) {
-      acc[ti][tj] = acc_t{};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dacc[ti][tj][v] = 0.0;
-    }
-  unsigned long long pairs = 0;
-  int any = 0;
-  // FP32: wave w owns the tile pairs (a, b) = (2 (w >> 2) + P, (w - a) & 3), P = 0, 1: the two waves
-  // of a SIMD (w, w + 4) take the 4 pairs with a + b = w (mod 4), one of every row and column of the
-  // 4 x 4 chunk pair, so a tile missing from a grid block costs every SIMD alike
-  const int ws = __builtin_amdgcn_readfirstlane(w);
-  const int pa0 = 2 * (ws >> 2), pb0 = (ws - pa0) & 3, pb1 = (ws - pa0 - 1) & 3;
-  // FP32: the diagonal pairs (a, a) of a diagonal chunk pair are k_vdiag's (FP64)
-  const int wdiag = (F32 && it.pc == it.qc) ? (((pa0 == pb0) ? 1 : 0) | ((pa0 + 1 == pb1) ? 2 : 0)) : 0;
-
-  for (int base = it.r0; base < it.r1; base += NTV) {
-    const int r = base + tid;
-    int mask = 0;
-    if (r < it.r1) mask = A.vmask[A.vmoff[r] - A.vm_base + it.lpair];
-    // exclusive prefix sum over the 8 waves (parallel addressing)
-    const unsigned long long bal = __ballot(mask != 0);
-    const int before = __popcll(bal & ((1ull << l) - 1ull));
-    if (l == 0) s_w[w] = __popcll(bal);
-    __syncthreads();
-    int pos = before, tot = 0;
-    for (int i = 0; i < 8; ++i) {
-      pos += (i < w) ? s_w[i] : 0;
-      tot += s_w[i];
-    }
-    if (mask) {
-      s_m[pos] = mask;
-      const int64_t cb = A.cioff[r];
-      s_ip[pos] = A.cinfo[cb + it.pc];
-      s_iq[pos] = A.cinfo[cb + it.qc];
-      s_bo[pos] = A.st.blk_off[r];
-      pairs += __popc(mask);
-    }
-    __syncthreads();
-    any |= tot;
-
-    if constexpr (F32) {
-      // sub-step st = kNS e + sub: entry e of the compacted list, points kSP sub .. kSP sub + kSP - 1.  Slot
-      // st % kRing: slab a < 4 is Phi_(4pc+a) and slab 4 + b is Z_(4qc+b), each [row i][point] with the
-      // 16-byte units of row i XOR-swizzled within groups of 8 (unit c at c ^ (i & 7)); wave w copies slab
-      // w, global -> LDS directly, one sub-step ahead, and only where the slab's tile has an executable
-      // pair.  MFMA step kk of 32-point half hp takes point 32 hp + 8 (l / 16) + kk of the sub-step, so a
-      // lane reads the 8 values of its row of a slab with two 16-byte loads.
-      float *ring = reinterpret_cast<float *>(s_raw);
-      const float *Pf = reinterpret_cast<const float *>(phi);
-      const float *Zf = reinterpret_cast<const float *>(zws);
-      const int m16 = l & 15, g = l >> 4;
-      const int nst = kNS * tot;
-      constexpr int kRowU = kSP / 4;                 // 16-byte units per slab row
-      constexpr int kCopies = kD * kRowU / 64;       // copies of 64 units per wave and slab
-      auto issue = [&](int st) {
-        const int e = st / kNS, sub = st % kNS;
-        const int m = __builtin_amdgcn_readfirstlane(s_m[e]);
-        const int slab = ws & 3;
-        const bool need = ws < 4 ? ((m >> (4 * slab)) & 15) != 0 : ((m >> slab) & 0x1111) != 0;
-        if (!need) return;
-        const int info = __builtin_amdgcn_readfirstlane(ws < 4 ? s_ip[e] : s_iq[e]);
-        const long long bo = s_bo[e];
-        const float *src = (ws < 4 ? Pf : Zf) + size_t(bo + tile_pos(info, slab)) * (kD * kG) + kSP * sub;
-        float *dst = ring + (st & (kRing - 1)) * kSlotF + ws * kSlab;
-#pragma unroll
-        for (int k = 0; k < kCopies; ++k) {
-          const int tu = 64 * k + l, i = tu / kRowU, cu = (tu % kRowU) ^ (i & 7);
-          dma16(src + i * kG + 4 * cu, dst + 256 * k);
-        }
-      };
-      static_assert(kRing == 2, "the waits below assume one sub-step in flight");
-      if (nst > 0) issue(0);
-      for (int st = 0; st < nst; ++st) {
-        // this wave's copies of sub-step st have landed and its reads of st - 1 are done; after the
-        // barrier the slot of st - 1 takes sub-step st + 1
-        wait_vm_lds<0>();
-        wg_barrier();
-        if (st + 1 < nst) issue(st + 1);
-        const int m = __builtin_amdgcn_readfirstlane(s_m[st / kNS]);
-        const float *sl = ring + (st & (kRing - 1)) * kSlotF;
-#pragma unroll
-        for (int P = 0; P < 2; ++P) {
-          const int a = pa0 + P, b = P ? pb1 : pb0;
-          if (!((m >> (4 * a + b)) & 1) || ((wdiag >> P) & 1)) continue;
-#pragma unroll
-          for (int hp = 0; hp < kSP / 32; ++hp) {
-            f4 fa[2][2], fb[2][2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-              for (int hh = 0; hh < 2; ++hh) {
-                const int off = (16 * t + m16) * kSP + 4 * ((8 * hp + 2 * g + hh) ^ (m16 & 7));
-                fa[t][hh] = *reinterpret_cast<const f4 *>(sl + a * kSlab + off);
-                fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + off);
-              }
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-              for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < 2; ++tj)
-                  acc[P][2 * ti + tj] =
-                      M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3], acc[P][2 * ti + tj]);
-            // FP32 sums of 32 points each, FP64 beyond
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) dacc[P][q][v] += double(acc[P][q][v]);
-              acc[P][q] = acc_t{};
-            }
-          }
-        }
-      }
-      __syncthreads();
-    } else {
-      // stages s = 4 e + sub: entry e of the compacted list, points 32 sub .. 32 sub + 31
-      constexpr int UR = kD / E;          // units per 32-element row slice
-      constexpr int UT = kD * UR;         // units per 32 x 32 slab
-      constexpr int NU = 8 * UT / NTV;    // units per thread (4 A slabs + 4 B slabs)
-      uint4 rv[NU];
-      int rmask = 0;
-      auto fetch = [&](int st) {
-        const int e = st >> 2, sub = st & 3;
-        const int m = s_m[e], ip = s_ip[e], iq = s_iq[e];
-        const int64_t bo = s_bo[e];
-        rmask = 0;
-#pragma unroll
-        for (int k = 0; k < NU; ++k) {
-          const int un = tid + NTV * k, which = un / UT, uu = un % UT;
-          const int i = uu / UR, j0 = (uu % UR) * E;
-          const int slot = which & 3;
-          // a row tile is needed if any of its pairs runs, a column tile likewise
-          const bool need = (which < 4) ? ((m >> (4 * slot)) & 15) != 0 : ((m >> slot) & 0x1111) != 0;
-          if (need) {
-            const int pos = tile_pos(which < 4 ? ip : iq, slot);
-            const T *src = ((which < 4) ? phi : zws) + size_t(bo + pos) * (kD * kG) + i * kG + 32 * sub + j0;
-            rv[k] = *reinterpret_cast<const uint4 *>(src);
-            rmask |= 1 << k;
-          }
-        }
-      };
-      auto stash = [&](int buf) {
-#pragma unroll
-        for (int k = 0; k < NU; ++k) {
-          if (!((rmask >> k) & 1)) continue;
-          const int un = tid + NTV * k, which = un / UT, uu = un % UT;
-          const int i = uu / UR, j0 = (uu % UR) * E;
-          T *dst = (which < 4) ? &sA[buf * kS + (32 * which + i) * LDA_S + j0]
-                                 : &sB[buf * kS + (32 * (which - 4) + i) * LDA_S + j0];
-          lds_store_unit<T>(dst, rv[k]);
-        }
-      };
-      const int nst = 4 * tot;
-      if (nst > 0) {
-        fetch(0);
-        stash(0);
-      }
-      __syncthreads();
-      for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        const int wm = (s_m[st >> 2] >> (4 * u + 2 * h)) & 3;   // this wave's two column tiles
-        if (st + 1 < nst) fetch(st + 1);
-        if (wm) {
-          const T *a = sA + buf * kS;
-          const T *b = sB + buf * kS;
-#pragma unroll 2
-          for (int kk = 0; kk < 8; ++kk) {
-            const int kc = 4 * kk + (l >> 4);
-            const T a0 = a[(32 * u + (l & 15)) * LDA_S + kc];
-            const T a1 = a[(32 * u + 16 + (l & 15)) * LDA_S + kc];
-#pragma unroll
-            for (int tj = 0; tj < 4; ++tj) {
-              if ((wm >> (tj >> 1)) & 1) {
-                const T bv = b[(64 * h + 16 * tj + (l & 15)) * LDA_S + kc];
-                acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
-                acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
-              }
-            }
-          }
-        }
-        if (st + 1 < nst) stash(buf ^ 1);
-        __syncthreads();
-      }
-    }
-  }
-  if (!any) {
-    if (tid == 0 && !A.accumulate) A.vflag[item] = 0;
-    return;
-  }
-  double *out = A.vpart + size_t(item) * (128 * 128);
-  if constexpr (F32) {
-#pragma unroll
-    for (int P = 0; P < 2; ++P) {
-      if ((wdiag >> P) & 1) continue;         // written by k_vdiag
-      const int a = pa0 + P, b = P ? pb1 : pb0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 32 * a + 16 * (q >> 1) + M::row(v, l), col = 32 * b + 16 * (q & 1) + (l & 15);
-          out[row * 128 + col] = dacc[P][q][v] + double(acc[P][q][v]);
-        }
-    }
-  } else {
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 4; ++tj) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 32 * u + 16 * ti + M::row(v, l), col = 64 * h + 16 * tj + (l & 15);
-          const double val = dacc[ti][tj][v] + double(acc[ti][tj][v]);
-          out[row * 128 + col] = prev ? out[row * 128 + col] + val : val;
-        }
-      }
-  }
-  if (tid == 0) A.vflag[item] = 1;
-  double pd = wave_sum(double(pairs));
-  if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
-  });
-}
-
 constexpr int NTV4 = 256;   // threads per FP32 Vxc workgroup: 4 waves, wave a owns row tile a (32 x 128)
 
 // FP32 operands: one workgroup of 4 waves per Vxc item (row chunk pc, column chunk qc, segment of grid
-// blocks), the same items and results as k_vgemm: M_pq = sum_r Phi_pr Z_qr^T over the executable grid
+// blocks): M_pq = sum_r Phi_pr Z_qr^T over the executable grid
 // blocks of the segment, compacted by prefix sum.  Its LDS (69 KB: a two-slot ring of one 32-point
 // sub-step each, 4 Phi slabs and 4 Z slabs of 32 x 32) lets two workgroups share a CU, so one
 // workgroup's copies, barriers and compaction overlap the other's MFMAs.  Wave a multiplies the Phi slab
@@ -1687,8 +1243,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
   });
 }
 
-// FP64 operands: the 4-wave Vxc kernel of k_vgemm_f32 on v_mfma_f64_16x16x4f64 (same items and results as
-// k_vgemm), with 16-point sub-steps so that a ring slot (4 Phi slabs and 4 Z slabs of 32 x 16) stays
+// FP64 operands: the 4-wave Vxc kernel of k_vgemm_f32 on v_mfma_f64_16x16x4f64 (same items), with 16-point sub-steps so that a ring slot (4 Phi slabs and 4 Z slabs of 32 x 16) stays
 // 32 KB; MFMA step kk takes point 4 (l / 16) + kk of the sub-step.  With `accumulate` set, an item whose
 // partial an earlier launch wrote adds to it (the meta-GGA term).
 __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
@@ -1819,9 +1374,9 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
 // One workgroup row per chunk pair (all molecules): FP64 sum of its segment partials in segment order.
 // FP32 plans: the diagonal tiles M_pp of the Vxc product in FP64.  One workgroup per Vxc item of a
 // diagonal chunk pair (pc = qc); wave w owns the tile p = 4 pc + w and walks the segment's blocks whose
-// pair mask executes (p, p) (eq. block_pair_filter, as k_vgemm), M_pp += Phi_pr Z_pr^T on FP64 MFMA with
+// pair mask executes (p, p) (eq. block_pair_filter, as k_vgemm_f32), M_pp += Phi_pr Z_pr^T on FP64 MFMA with
 // the operand Phi_hi + Phi_lo; the result goes to the tile's place in the item's partial, whose other
-// tiles k_vgemm writes.  The two kernels share no output, so they run concurrently (an item in which
+// tiles k_vgemm_f32 writes.  The two kernels share no output, so they run concurrently (an item in which
 // nothing executes gets zeros here and is skipped by the reduction).
 struct VDArgs {
   StructDev st;
@@ -1837,6 +1392,7 @@ struct VDArgs {
   const unsigned short *phil;
   const float *zws;
   double *vpart;
+  unsigned long long *counters;
 };
 
 __global__ __launch_bounds__(NT) void k_vdiag(VDArgs A) {
@@ -1846,9 +1402,11 @@ __global__ __launch_bounds__(NT) void k_vdiag(VDArgs A) {
   d4 dd[2][2];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti) dd[ti][0] = dd[ti][1] = d4{0.0, 0.0, 0.0, 0.0};
+  int n_exec = 0;
   for (int r = it.r0; r < it.r1; ++r) {
     const int mask = A.vmask[A.vmoff[r] - A.vm_base + it.lpair];
     if (!((mask >> (5 * w)) & 1)) continue;      // bit 4 w + w: the pair (p, p)
+    ++n_exec;
     const int ci = A.cinfo[A.cioff[r] + it.pc];
     const size_t t = size_t(A.st.blk_off[r] + tile_pos(ci, w) - A.ret0) * (kD * kG);
     // MFMA step kk of lane group g = l / 16 takes point 32 g + kk, so a lane reads 8 consecutive points
@@ -1895,6 +1453,7 @@ __global__ __launch_bounds__(NT) void k_vdiag(VDArgs A) {
         const int row = 32 * w + 16 * ti + Mma<double>::row(v, l), col = 32 * w + 16 * tj + (l & 15);
         out[row * 128 + col] = dd[ti][tj][v];
       }
+  if (l == 0 && n_exec > 0) atomicAdd(&A.counters[6], (unsigned long long)n_exec);
 }
 
 __global__ __launch_bounds__(NT) void k_vreduce(const int *pair_ptr, const int *pair_items, const int *pair_info,
@@ -2058,9 +1617,9 @@ void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
         k_xgemm_f64<false><<<gx, NTX4, 0, s>>>(xa);
     } else {
       if (P.gga)
-        k_xgemm<T, true, NPC><<<gx, NTX, 0, s>>>(xa);
+        k_xgemm_bf16<true, NPC><<<gx, NTX, 0, s>>>(xa);
       else
-        k_xgemm<T, false, NPC><<<gx, NTX, 0, s>>>(xa);
+        k_xgemm_bf16<false, NPC><<<gx, NTX, 0, s>>>(xa);
     }
     if constexpr (sizeof(T) == 8 && NPC == 0) {
       if (is_mgga_xc(P.opts.xc)) {
@@ -2102,7 +1661,7 @@ void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
   }
 }
 
-// Arguments of a k_vgemm launch over the Vxc items of grid chunk ci with operands A (rows) and B.
+// Arguments of a Vxc GEMM launch over the Vxc items of grid chunk ci with operands A (rows) and B.
 VArgs v_args(const Plan &P, size_t ci, const void *A, const void *B) {
   const EvalDev &E = P.ev;
   const GridChunk &C = P.chunks_h[ci];
@@ -2190,8 +1749,8 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
       const int64_t gv = 8 * P.vq.maxlen_h[ci];
       const int64_t nd = P.dchunk_h[ci + 1] - P.dchunk_h[ci];
       const bool diag = sizeof(T) == 4 && nd > 0;
-      // k_vdiag needs what k_vmask and the stages before it wrote and shares no output with k_vgemm: it
-      // runs on the side stream beside k_vgemm, which joins back before the next use of the workspaces
+      // k_vdiag needs what k_vmask and the stages before it wrote and shares no output with k_vgemm_f32: it
+      // runs on the side stream beside k_vgemm_f32, which joins back before the next use of the workspaces
       if (diag) {
         hipError_t e = hipEventRecord(P.fork_ev, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(P.side_stream, P.fork_ev, 0);
@@ -2236,6 +1795,7 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
         da.phil = E.phil;
         da.zws = static_cast<const float *>(E.zws);
         da.vpart = E.vpart;
+        da.counters = E.counters;
         k_vdiag<<<nd, NT, 0, P.side_stream>>>(da);
         hipError_t e = hipEventRecord(P.join_ev, P.side_stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, P.join_ev, 0);
@@ -2259,7 +1819,7 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
 // Nuclear gradient of E_xc with the grid held fixed (FP64 plans of one molecule):
 //   dE/dR_Aa = -2 sum_{mu on A} sum_nu D_{mu nu} K^a_{mu nu},  K^a = (d_a Phi) W^T + Q^a Phi^T,
 //   W = c0 Phi + sum_b c_b d_b Phi,  Q^a = sum_b c_b d_a d_b Phi,  c0 = w v_rho,  c_b = 2 w v_sigma d_b rho.
-// The products run on k_vgemm over the Vxc work items, tile pairs (p, q) executing at block r when
+// The products run on k_vgemm_f64 over the Vxc work items, tile pairs (p, q) executing at block r when
 // (p, r), (q, r) are retained and a_pq >= t_b; each item's partial is contracted with D at once.
 // LDA plans hold the chunk pairs pc <= qc only: there the pairs pc < qc also run the product with
 // its operands exchanged, W (d_a Phi)^T = (K^a)^T for the transposed chunk pair, contracted along columns.

@@ -220,7 +220,7 @@ struct Plan {
   bool use_graph = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
-  // FP32 plans: k_vdiag runs on a side stream forked from the evaluation's stream before k_vgemm and
+  // FP32 plans: k_vdiag runs on a side stream forked from the evaluation's stream before k_vgemm_f32 and
   // joined back after it (default priority, non-blocking)
   hipStream_t side_stream = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;

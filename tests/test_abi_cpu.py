@@ -37,7 +37,7 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_version_and_defaults(L):
-    assert L.kldi_version() == 3
+    assert L.kldi_version() == 4
     o = L.kldi_opts()
     L.kldi_opts_default(ctypes.byref(o))
     assert o.t_b == 1e-10 and o.t_d == 1e-10 and o.rho_cut == 1e-14

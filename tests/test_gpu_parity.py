@@ -96,8 +96,12 @@ def test_cfg0_fp64_and_fp32(Plan, cfg0):
     assert np.abs(g["V"] - ref["V"]).max() <= 1e-12 * np.abs(ref["V"]).max()
     assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * np.abs(ref["rho"]).max()
     assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
+    assert g["stats"]["n_pairs_v_diag"] == 0
     # spec accuracy of the FP32 form against the unscreened FP64 oracle
     f = run(Plan, p, "lda", "fp32")
+    # the FP32 plan runs the same triples, its diagonal ones (p, p, r) on the FP64 diagonal kernel
+    assert (f["stats"]["n_pairs_x"], f["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
+    assert f["stats"]["n_pairs_v_diag"] == ref["nP_M_diag"] > 0
     assert abs(f["E"] - dense["E"]) < 1e-6
     assert np.abs(f["V"] - dense["V"]).max() < 1e-7
     big = dense["rho"] > 1e-8
@@ -169,7 +173,8 @@ def test_grid_chunks_give_identical_results(Plan, cfg0, xc, prec):
     assert na == 1 and nb > 1
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
-    assert (sa["n_pairs_x"], sa["n_pairs_v"]) == (sb["n_pairs_x"], sb["n_pairs_v"])
+    assert (sa["n_pairs_x"], sa["n_pairs_v"], sa["n_pairs_v_diag"]) == (sb["n_pairs_x"], sb["n_pairs_v"],
+                                                                         sb["n_pairs_v_diag"])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x3"])

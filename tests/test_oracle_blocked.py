@@ -116,7 +116,8 @@ def test_stream_evaluation_equals_blocked(xc, t):
     args = (p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc)
     ref = oracle.eval_blocked(*args, t_b=t, t_d=t)
     s = oracle.blocked.eval_blocked_stream(*args, t_b=t, t_d=t, blocks_per_chunk=3)
-    assert (s["nP_X"], s["nP_M"]) == (ref["nP_X"], ref["nP_M"])
+    assert (s["nP_X"], s["nP_M"], s["nP_M_diag"]) == (ref["nP_X"], ref["nP_M"], ref["nP_M_diag"])
+    assert 0 < ref["nP_M_diag"] < ref["nP_M"]
     assert abs(s["E"] - ref["E"]) <= 1e-13 * abs(ref["E"])
     assert np.abs(s["rho"] - ref["rho"]).max() <= 1e-13 * np.abs(ref["rho"]).max()
     assert np.abs(s["V"] - ref["V"]).max() <= 1e-13 * np.abs(ref["V"]).max()
