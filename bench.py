@@ -45,6 +45,12 @@ WORKLOADS = {
     2: "1000-atom cluster, 10,000 cartesian AOs, 22.65M points (75x302 per atom), 128-point blocks, 32-AO tiles, "
        "PBE, t_b=t_d=1e-10",
 }
+# screening block (grid_block) of each workload's recipe: the 1000- and 500-atom clusters use 256 points
+DEFAULT_G = {0: 128, 1: 128, 2: 256, 3: 128, 4: 256}
+
+
+def workload_name(config, G):
+    return WORKLOADS.get(config, "config %d" % config).replace("128-point blocks", "%d-point blocks" % G)
 
 
 def kernels_sha1():
@@ -321,7 +327,7 @@ def bench_learned(args, torch):
     D4 = torch.from_numpy(p4.D).cuda()
     log("inputs: %s n_atoms=%d n_ao=%d n_points=%d" % (p4.name, p4.n_atoms, p4.n_ao, p4.n_points))
     # the functional alone on this workload's (rho, sigma): analytic PBE (FP64) vs the network
-    plan = Plan.from_problem(p4, prec="fp32", xc="pbe")
+    plan = Plan.from_problem(p4, prec="fp32", xc="pbe", grid_block=args.grid_block)
     r4, s4 = plan.eval_grid(D4)
     plan.close()
     torch.cuda.synchronize()
@@ -343,7 +349,7 @@ def bench_learned(args, torch):
     torch.cuda.empty_cache()
     out_runs = {}
     for tag in ("analytic", "mlp"):
-        plan = Plan.from_problem(p4, prec="fp32", xc="pbe")
+        plan = Plan.from_problem(p4, prec="fp32", xc="pbe", grid_block=args.grid_block)
         if tag == "mlp":
             plan.attach_mlp(net)
         ms, stage, st, E, V, rho = time_path(plan, D4, args.steps, args.warmup, torch)
@@ -353,7 +359,7 @@ def bench_learned(args, torch):
         plan.close()
         del rho
         torch.cuda.empty_cache()
-    plan = Plan.from_problem(p4, prec="fp64", xc="pbe")
+    plan = Plan.from_problem(p4, prec="fp64", xc="pbe", grid_block=args.grid_block)
     ms64, stage64, st64, E64, V64, rho64 = time_path(plan, D4, 1, 1, torch)
     plan.close()
     a, m = out_runs["analytic"], out_runs["mlp"]
@@ -361,8 +367,9 @@ def bench_learned(args, torch):
         "metric": METRIC, "value": round(m["ms"], 4), "unit": "ms/eval", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(m["ms"], 4), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "500-atom cluster, 5000 cartesian AOs, %d points (75x302 per atom), 128-point blocks, "
-                               "PBE replaced by the trained network where it covers a point" % p4.n_points,
+        "config": {"workload": "500-atom cluster, 5000 cartesian AOs, %d points (75x302 per atom), %d-point blocks, "
+                               "PBE replaced by the trained network where it covers a point" % (p4.n_points,
+                                                                                                 args.grid_block),
                    "path": "mixed FP32 block GEMMs; BF16-weight MLP functional, analytic fallback"},
         "learned": {
             "train_points": n_train, "train_sources": "4.53M points of the 200-atom chain + 5.47M of the 1000-atom cluster",
@@ -418,12 +425,17 @@ def main():
     ap.add_argument("--precs", default="fp32,bf16x6,bf16x3",
                     help="precision forms timed beside FP64 (workloads 1 and 2); the first is the headline value")
     ap.add_argument("--v-segment", type=int, default=0, help="grid blocks per Vxc segment (0 = plan's choice)")
+    ap.add_argument("--grid-block", type=int, default=0,
+                    help="points per screening block, 128 or 256 (0 = the workload's recipe: 256 for workloads 2 "
+                         "and 4, else 128)")
     ap.add_argument("--schedule", default="grid", choices=["grid", "queue", "auto"],
                     help="work-item schedule of the GEMM kernels (auto: the plan's autotuner picks it and the "
                          "Vxc segment length, outside the timed region)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM-counter calibration for profiling)")
     args = ap.parse_args()
+    if args.grid_block == 0:
+        args.grid_block = DEFAULT_G.get(args.config, 128)
     if args.gpus != 1:
         print("bench.py runs on one GPU only (libkldi has no multi-GPU path); got --gpus %d" % args.gpus)
         sys.exit(2)
@@ -462,14 +474,14 @@ def main():
     if args.sweep:
         gd = json.load(open(GOLDEN))
         rows = sweep(p, D, args.steps, args.warmup, torch, Plan, gd, so)
-        print(json.dumps({"workload": WORKLOADS.get(args.config), "sweep": rows}), flush=True)
+        print(json.dumps({"workload": workload_name(args.config, args.grid_block), "sweep": rows}), flush=True)
         return
     res = {}
     forms = [f for f in args.precs.split(",") if f]
     for prec in (forms if args.no_fp64 else forms + ["fp64"]):
         torch.cuda.synchronize()
         t0 = time.time()
-        plan = Plan.from_problem(p, prec=prec, v_segment=args.v_segment, shell_order=so,
+        plan = Plan.from_problem(p, prec=prec, v_segment=args.v_segment, shell_order=so, grid_block=args.grid_block,
                                  schedule="grid" if args.schedule == "auto" else args.schedule)
         tune = plan.autotune(D, reps=2) if args.schedule == "auto" else None
         info = plan.info()
@@ -496,7 +508,7 @@ def main():
         "metric": METRIC, "value": round(mix["ms"], 4), "unit": "ms/eval", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(mix["ms"], 4), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPE[forms[0]], "data": "synthetic",
-        "config": {"workload": WORKLOADS.get(args.config, "config %d" % args.config),
+        "config": {"workload": workload_name(args.config, args.grid_block),
                    "path": PATHS[forms[0]],
                    "basis_order": "overlap-signature clustering" if so is not None else "atom order",
                    "seeds": p.meta.get("seeds")},
@@ -542,7 +554,7 @@ def main():
                 out["err_vs_oracle"]["%s_%s" % (tag, prec)] = {"E_xc": abs(r["E"] - g["E"]), "V_maxabs_sampled": dv}
 
     if args.config == 1 and not args.no_dense:
-        plan = Plan.from_problem(p, prec=forms[0], t_b=0.0, t_d=0.0, shell_order=so)
+        plan = Plan.from_problem(p, prec=forms[0], t_b=0.0, t_d=0.0, shell_order=so, grid_block=args.grid_block)
         info = plan.info()
         ms, stage, st, E, V, rho = time_path(plan, D, max(3, args.steps // 2), 1, torch)
         log("%s unscreened (t_b = t_d = 0): %.3f ms/eval, %d chunks, pairs x %d v %d" % (
@@ -561,7 +573,7 @@ def main():
         if so is None:
             from paper_2605_10363_amd.plan import overlap_order
             _, so2 = overlap_order(p.basis, synth.overlap_matrix(p.basis, p.atom_xyz))
-        plan = Plan.from_problem(p, prec=forms[0], v_segment=args.v_segment, shell_order=so2)
+        plan = Plan.from_problem(p, prec=forms[0], v_segment=args.v_segment, shell_order=so2, grid_block=args.grid_block)
         info = plan.info()
         ms, stage, st, E, V, rho = time_path(plan, D, args.steps, args.warmup, torch)
         log("%s, %s: %.3f ms/eval, retained fraction %.4f, pairs x %d v %d" % (

@@ -636,14 +636,16 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) dma16(ps + 4 * (64 * m + l), dst + 4 * kD * kD + 1024 * ws + 256 * m);
   };
+  // the FP32 window of row 0 is steps 4-7 of one computed entry and steps 0-3 of the next, that of row 1
+  // steps 0-7 of one entry; a window's first MFMA takes a zero accumulator (no register clearing), and the
+  // epilogue adds the window still open
   auto flush = [&](int ti) {
 #pragma unroll
-    for (int tj = 0; tj < 8; ++tj) {
+    for (int tj = 0; tj < 8; ++tj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) dacc[ti][tj][v] += double(acc[ti][tj][v]);
-      acc[ti][tj] = f4{0.f, 0.f, 0.f, 0.f};
-    }
   };
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
   if (n_list > 0) issue(0);
   // entry e: wait until this wave's copies of e have landed and its reads of e - 1 are done; after the
   // barrier the slot of e - 1 takes e + 1
@@ -669,8 +671,8 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
 #pragma unroll
         for (int tj = 0; tj < 8; ++tj) {
           const float bv = tj < 4 ? b0[tj] : b1[tj - 4];
-          acc[0][tj] = M::mma(a0, bv, acc[0][tj]);
-          acc[1][tj] = M::mma(a1, bv, acc[1][tj]);
+          acc[0][tj] = M::mma(a0, bv, kk == 4 ? zero : acc[0][tj]);
+          acc[1][tj] = M::mma(a1, bv, kk == 0 ? zero : acc[1][tj]);
         }
         if (kk == 3) flush(0);
         if (kk == 7) flush(1);
@@ -697,7 +699,7 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             Xw[(16 * ti + M::row(v, l)) * kG + 64 * (tj >> 2) + 4 * m16 + (tj & 3)] =
-                dacc[ti][tj][v] + double(acc[ti][tj][v]);
+                ti == 0 ? dacc[ti][tj][v] + double(acc[ti][tj][v]) : dacc[ti][tj][v];   // row 1: flushed
     }
     __syncthreads();
     const int slot = 4 * c + 2 * R + slot_w;
@@ -1171,6 +1173,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
         }
       }
     };
+    const f4 zero = {0.f, 0.f, 0.f, 0.f};
     if (nst > 0) issue(0);
     for (int st = 0; st < nst; ++st) {
       // this wave's copies of sub-step st have landed and its reads of st - 1 are done; after the
@@ -1198,22 +1201,21 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
             for (int hh = 0; hh < 2; ++hh)
               fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + (16 * t + m16) * kSP +
                                                         4 * ((2 * g + hh) ^ (m16 & 7)));
+          // FP32 sums of 32 points each (the first MFMA takes a zero accumulator), FP64 beyond
 #pragma unroll
           for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
             for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
               for (int tj = 0; tj < 2; ++tj)
-                acc[ti][2 * b + tj] = M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3], acc[ti][2 * b + tj]);
-          // FP32 sums of 32 points each, FP64 beyond
+                acc[ti][2 * b + tj] = M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3],
+                                             kk == 0 ? zero : acc[ti][2 * b + tj]);
 #pragma unroll
           for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < 2; ++tj) {
+            for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
               for (int v = 0; v < 4; ++v) dacc[ti][2 * b + tj][v] += double(acc[ti][2 * b + tj][v]);
-              acc[ti][2 * b + tj] = f4{0.f, 0.f, 0.f, 0.f};
-            }
         }
       }
     }
