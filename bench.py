@@ -119,10 +119,14 @@ def gemm_rooflines(prec, stats, stage):
     return out
 
 
-def cpu_baseline(p, n_sample=300000, seed=0):
+def cpu_baseline(p, n_sample=None, seed=0):
     """The FP64 oracle (dense, NumPy + host BLAS) on a random sample of grid points, scaled to one
-    full evaluation (its cost is linear in the number of points)."""
+    full evaluation (its cost is linear in the number of points).  The sample is sized for about 15 s of
+    host work: 300,000 points at 2000 AOs, fewer for larger bases (the cost per point grows faster than
+    the AO count)."""
     import oracle
+    if n_sample is None:
+        n_sample = int(300000 * min(1.0, (2000.0 / p.n_ao) ** 1.5))
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(p.n_points, size=min(n_sample, p.n_points), replace=False))
     t0 = time.perf_counter()

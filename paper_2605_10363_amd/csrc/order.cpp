@@ -36,21 +36,37 @@ int ncart_l(int l) { return (l + 1) * (l + 2) / 2; }
 // condensed index of (i, j), i < j, in the row-major upper triangle of an n x n matrix
 inline size_t cidx(size_t n, size_t i, size_t j) { return i * n - i * (i + 1) / 2 + (j - i - 1); }
 
-// Gram matrix of the normalised rows, as cosine distances in condensed form (host threads over rows)
+// Gram matrix of the normalised rows, as cosine distances in condensed form.  Host threads take blocks
+// of 4 rows (dealt cyclically: block i has n - 4 i entries to its right, so the work evens out); each
+// 4 x 4 block of the upper triangle keeps 16 sums in registers, each summed over k in order (the same
+// sum as one dot product at a time, 8x fewer loads).
 void cosine_distances(const std::vector<double> &U, size_t n, std::vector<double> &d) {
   d.assign(n * (n - 1) / 2, 0.0);
+  const size_t nb = (n + 3) / 4;
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<std::thread> th;
   for (unsigned t = 0; t < nt; ++t) {
     th.emplace_back([&, t] {
-      // rows dealt cyclically: row i has n - i - 1 entries, so the work evens out
-      for (size_t i = t; i < n; i += nt) {
-        const double *ui = U.data() + i * n;
-        for (size_t j = i + 1; j < n; ++j) {
-          const double *uj = U.data() + j * n;
-          double s = 0.0;
-          for (size_t k = 0; k < n; ++k) s += ui[k] * uj[k];
-          d[cidx(n, i, j)] = 1.0 - s;
+      for (size_t ib = t; ib < nb; ib += nt) {
+        const size_t i0 = 4 * ib, ni = std::min<size_t>(4, n - i0);
+        const double *u[4];
+        for (size_t a = 0; a < 4; ++a) u[a] = U.data() + std::min(i0 + a, n - 1) * n;
+        for (size_t jb = ib; jb < nb; ++jb) {
+          const size_t j0 = 4 * jb, nj = std::min<size_t>(4, n - j0);
+          const double *v[4];
+          for (size_t b = 0; b < 4; ++b) v[b] = U.data() + std::min(j0 + b, n - 1) * n;
+          double s[4][4] = {};
+          for (size_t k = 0; k < n; ++k) {
+            const double x0 = u[0][k], x1 = u[1][k], x2 = u[2][k], x3 = u[3][k];
+            const double y0 = v[0][k], y1 = v[1][k], y2 = v[2][k], y3 = v[3][k];
+            s[0][0] += x0 * y0; s[0][1] += x0 * y1; s[0][2] += x0 * y2; s[0][3] += x0 * y3;
+            s[1][0] += x1 * y0; s[1][1] += x1 * y1; s[1][2] += x1 * y2; s[1][3] += x1 * y3;
+            s[2][0] += x2 * y0; s[2][1] += x2 * y1; s[2][2] += x2 * y2; s[2][3] += x2 * y3;
+            s[3][0] += x3 * y0; s[3][1] += x3 * y1; s[3][2] += x3 * y2; s[3][3] += x3 * y3;
+          }
+          for (size_t a = 0; a < ni; ++a)
+            for (size_t b = 0; b < nj; ++b)
+              if (j0 + b > i0 + a) d[cidx(n, i0 + a, j0 + b)] = 1.0 - s[a][b];
         }
       }
     });
