@@ -561,6 +561,28 @@ def main():
                          np.abs(np.diag(V) - np.array(g["v_diag"])).max())
                 out["err_vs_oracle"]["%s_%s" % (tag, prec)] = {"E_xc": abs(r["E"] - g["E"]), "V_maxabs_sampled": dv}
 
+    if args.config == 1 and not args.no_fp64:
+        # the nuclear gradient of E_xc with the grid held fixed (FP64 plans), beside the energy evaluation
+        plan = Plan.from_problem(p, prec="fp64", shell_order=so)
+        g = plan.grad(D)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = max(2, args.steps // 2)
+        e0.record()
+        for _ in range(reps):
+            g = plan.grad(D)
+        e1.record()
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / reps
+        gn = g.cpu().numpy()
+        log("fp64 gradient: %.3f ms, max |dE/dR| %.3e" % (gms, np.abs(gn).max()))
+        out["gradient"] = {"what": "dE_xc/dR of all %d atoms (grid held fixed), FP64 plan, one kldi_eval_grad call "
+                                   "(its own rho, functional and the gradient products)" % p.n_atoms,
+                           "ms": round(gms, 3), "ratio_to_fp64_energy_eval": round(gms / res["fp64"]["ms"], 3)
+                           if "fp64" in res else None, "max_abs": float(np.abs(gn).max())}
+        plan.close()
+        torch.cuda.empty_cache()
     if args.config == 1 and not args.no_dense:
         plan = Plan.from_problem(p, prec=forms[0], t_b=0.0, t_d=0.0, shell_order=so, grid_block=args.grid_block)
         info = plan.info()
