@@ -399,12 +399,15 @@ kldi_status kldi_eval_timing(kldi_plan *plan, double *stage_ms, int32_t *n_evals
  *   dE_xc/dR_Aa = -2 sum_{mu on A} sum_nu D_{mu nu} K^a_{mu nu},
  *   K^a = (d_a Phi) W^T + Q^a Phi^T,  W = w v_rho Phi + sum_b c_b d_b Phi,  Q^a = sum_b c_b d_a d_b Phi,
  * c_b = 2 w v_sigma d_b rho (zero for LDA), evaluated like the energy: Phi on retained tiles, rho and
- * the functional as kldi_eval, and the products of the Vxc shape on the tile pairs (p, q) whose
- * operands are retained at a grid block and whose D block is retained (a_pq >= t_b).
+ * the functional as kldi_eval, and each product A B^T of the Vxc shape on the tile triples (p, q, r)
+ * whose operands are retained at grid block r, whose D block is retained (a_pq >= t_b) and whose
+ * contribution bound a_pq max|A_pr| max|B_qr| reaches t_d (the pair filter of eq. block_pair_filter for
+ * the three factors; a reading: the paper states no filter for the gradient).
  *   D_dev     as for kldi_eval (device, n_ao x n_ao, caller order)
  *   grad_dev  [n_atoms * 3] device, caller atom order, (x, y, z) per atom, Eh/bohr
  *   exc_dev   1 double on the device, or NULL: E_xc of the same evaluation
- * Single-molecule plans with KLDI_PREC_FP64 and the analytic functional (else KLDI_E_UNSUPPORTED).
+ * Single-molecule plans with KLDI_PREC_FP64, 128-point blocks and the analytic functional (else
+ * KLDI_E_UNSUPPORTED).
  * Allocates its workspaces on the plan on first use (KLDI_E_OOM if they do not fit); only enqueues
  * work on `stream`. */
 kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_dev, double *exc_dev, void *stream);

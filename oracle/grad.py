@@ -69,20 +69,29 @@ def exc_gradient(atom_xyz, basis, pts, weights, D, xc, rho_cut=1e-14, chunk=2048
     return out
 
 
-def exc_gradient_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, d_ao=32, G=128,
-                         rho_cut=1e-14, shell_order=None):
+def exc_gradient_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_d=None, d_ao=32, G=128,
+                         rho_cut=1e-14, shell_order=None, return_count=False, t_grad=None):
     """The gradient of the block-filtered evaluation: rho, grad rho and the functional exactly as
-    oracle.blocked.eval_blocked computes them at thresholds (t_b, t_d = t_b), then
+    oracle.blocked.eval_blocked computes them at thresholds (t_b, t_d; t_d = t_b when not given), then
         dE/dR_Aa = -2 sum_{mu on A} sum_nu D_{mu nu} K^a_{mu nu},
-    K^a_{pq} = sum_{r : (p,r), (q,r) in S_Phi} [(d_a Phi)_pr W_qr^T + Q^a_pr Phi_qr^T] over the tile pairs
-    (p, q) whose D block is retained (a_pq >= t_b).  Reading: the gradient products execute every tile
-    pair of retained operands with a retained D block; the paper states no filter for the gradient."""
+    K^a_{pq} = sum over executed (p, q, r) of (d_a Phi)_pr W_qr^T + Q^a_pr Phi_qr^T, each of the two products
+    executing its own tile triples.  Reading (the paper states no filter for the gradient): a product
+    A B^T contracted with D executes (p, q, r) when both operand tiles are retained at block r, the D block
+    is retained (a_pq >= t_b), and the bound of the triple's contribution passes the pair threshold,
+        a_pq * max|A_pr| * max|B_qr| >= t_d,
+    the analogue of eq. block_pair_filter for a three-factor term (t_grad, the products' threshold, is t_d
+    unless given: the library uses t_d).  return_count: also the number of executed triples over all axes
+    and products."""
     from . import blocked as _blocked
+    if t_d is None:
+        t_d = t_b
+    if t_grad is None:
+        t_grad = t_d
     atom_xyz = np.asarray(atom_xyz, np.float64)
     pts = np.asarray(pts, np.float64)
     w = np.asarray(weights, np.float64)
     gga = _fx.is_gga(xc)
-    ref = _blocked.eval_blocked(atom_xyz, basis, pts, w, point_atom, D, xc, t_b=t_b, t_d=t_b, d_ao=d_ao, G=G,
+    ref = _blocked.eval_blocked(atom_xyz, basis, pts, w, point_atom, D, xc, t_b=t_b, t_d=t_d, d_ao=d_ao, G=G,
                                 rho_cut=rho_cut, shell_order=shell_order)
     ao_perm, pt_perm = ref["ao_perm"], ref["pt_perm"]
     nao = len(ao_perm)
@@ -104,22 +113,30 @@ def exc_gradient_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1
     W = c0[None, :] * phi
     if gga:
         W = W + np.einsum("bi,bmi->mi", cb, dphi)
+
+    def tile_max(X):
+        return np.array([[np.max(np.abs(X[t0:t1, r0:r1])) for (r0, r1) in B] for (t0, t1) in T])
+
+    count = 0
     for ax in range(3):
-        Q = np.einsum("bi,bmi->mi", cb, hphi[ax]) if gga else None
+        products = [(dphi[ax], W)]
+        if gga:
+            products.append((np.einsum("bi,bmi->mi", cb, hphi[ax]), phi))
         K = np.zeros((nao, nao))
-        for ip, (p0, p1) in enumerate(T):
-            for iq, (q0, q1) in enumerate(T):
-                if not a[ip, iq] >= t_b:
-                    continue
-                for ir, (r0, r1) in enumerate(B):
-                    if S_phi[ip, ir] and S_phi[iq, ir]:
-                        K[p0:p1, q0:q1] += dphi[ax][p0:p1, r0:r1] @ W[q0:q1, r0:r1].T
-                        if gga:
-                            K[p0:p1, q0:q1] += Q[p0:p1, r0:r1] @ phi[q0:q1, r0:r1].T
+        for (Aop, Bop) in products:
+            mA, mB = tile_max(Aop), tile_max(Bop)
+            for ip, (p0, p1) in enumerate(T):
+                for iq, (q0, q1) in enumerate(T):
+                    if not a[ip, iq] >= t_b:
+                        continue
+                    for ir, (r0, r1) in enumerate(B):
+                        if S_phi[ip, ir] and S_phi[iq, ir] and a[ip, iq] * mA[ip, ir] * mB[iq, ir] >= t_grad:
+                            K[p0:p1, q0:q1] += Aop[p0:p1, r0:r1] @ Bop[q0:q1, r0:r1].T
+                            count += 1
         g_ao[ax] = np.sum(Dp * K, axis=1)
     ncart = [(int(l) + 1) * (int(l) + 2) // 2 for l in basis.shell_l]
     atom_of_ao = np.repeat(np.asarray(basis.shell_atom, np.int64), ncart)[ao_perm]
     out = np.zeros((atom_xyz.shape[0], 3))
     for ax in range(3):
         np.add.at(out[:, ax], atom_of_ao, -2.0 * g_ao[ax])
-    return out
+    return (out, count) if return_count else out

@@ -1248,9 +1248,12 @@ kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_de
     if (P.opts.prec != KLDI_PREC_FP64) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient runs on FP64 plans");
     if (P.has_mlp) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient needs the analytic functional");
     if (kldi::is_mgga_xc(P.opts.xc)) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient covers LDA and GGA functionals");
+    if (P.opts.grid_block != kldi::kG) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient runs on 128-point blocks");
     kldi::check_hip(hipSetDevice(P.device), "hipSetDevice");
     if (!P.grad_ws.gA) {
       P.grad_ws.gA = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.max_ret, 1)) * 4096, true);
+      P.grad_ws.gAmax = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.max_ret, 1)), true);
+      P.grad_ws.gWmax = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.max_ret, 1)), true);
       P.grad_ws.gitem = kldi::dev_alloc<double>(P, std::max<size_t>(P.items_h.size(), 1) * 6 * 128, true);
       P.grad_ws.gao = kldi::dev_alloc<double>(P, size_t(3) * P.mols_h[0].nc * 128, true);
     }

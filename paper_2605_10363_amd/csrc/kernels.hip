@@ -1093,11 +1093,15 @@ constexpr int NTV4 = 256;   // threads per FP32 Vxc workgroup: 4 waves, wave a o
 // blocks): M_pq = sum_r Phi_pr Z_qr^T over the executable grid
 // blocks of the segment, compacted by prefix sum.  Its LDS (69 KB: a two-slot ring of one 32-point
 // sub-step each, 4 Phi slabs and 4 Z slabs of 32 x 32) lets two workgroups share a CU, so one
-// workgroup's copies, barriers and compaction overlap the other's MFMAs.  Wave a multiplies the Phi slab
-// of row tile a by the 4 Z slabs; MFMA step kk takes point 8 (l / 16) + kk of the sub-step, so a lane
-// reads the 8 values of its row of a slab with two 16-byte loads.  The FP32 accumulators of a column tile
-// are added to the FP64 sums after each sub-step (32 points).  The diagonal pairs (a, a) of a diagonal
-// chunk pair are k_vdiag's (FP64).
+// workgroup's copies, barriers and compaction overlap the other's MFMAs.  Wave w owns the tile pairs
+// (a, (w - a) mod 4), a = 0..3: one of every row and every column of the 4 x 4 chunk pair.  A block's
+// pair mask is sparse (about 4 of 16 pairs execute at the bench workload) and close to the outer product
+// of the retained row and column tiles, which this ownership spreads over the 4 waves (owning a row each
+// left the waves of unretained rows idle: 41.8 ms against 35.9 ms for the Vxc stage of the bench
+// workload).  MFMA step kk takes point 8 (l / 16) + kk of the sub-step, so a lane reads the 8 values of
+// its row of a slab with two 16-byte loads.  The FP32 accumulators of a pair are added to the FP64 sums
+// after each sub-step (32 points).  The diagonal pairs (a, a) of a diagonal chunk pair are k_vdiag's
+// (FP64).
 __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
   typedef Mma<float> M;
   constexpr int kSP = 32, kNS = kG / kSP, kSlab = kD * kSP, kSlot = 8 * kSlab;
@@ -1181,42 +1185,37 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
       wait_vm_lds<0>();
       wg_barrier();
       if (st + 1 < nst) issue(st + 1);
-      const int m = (__builtin_amdgcn_readfirstlane(s_m[st / kNS]) >> (4 * ws)) & ((diag ? ~(1 << ws) : 15) & 15);
-      if (m) {
-        const float *sl = ring + (st & 1) * kSlot;
-        f4 fa[2][2];
+      const int m = __builtin_amdgcn_readfirstlane(s_m[st / kNS]);
+      const float *sl = ring + (st & 1) * kSlot;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        // pair a of this wave: row tile a, column tile b = (w - a) mod 4; accumulators 2a, 2a + 1
+        const int b = (ws - a) & 3;
+        if (!((m >> (4 * a + b)) & 1) || (diag && a == b)) continue;
+        f4 fa[2][2], fb[2][2];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-          for (int hh = 0; hh < 2; ++hh)
-            fa[t][hh] = *reinterpret_cast<const f4 *>(sl + ws * kSlab + (16 * t + m16) * kSP +
-                                                      4 * ((2 * g + hh) ^ (m16 & 7)));
+          for (int hh = 0; hh < 2; ++hh) {
+            const int off = (16 * t + m16) * kSP + 4 * ((2 * g + hh) ^ (m16 & 7));
+            fa[t][hh] = *reinterpret_cast<const f4 *>(sl + a * kSlab + off);
+            fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + off);
+          }
+        // FP32 sums of 32 points each (the first MFMA takes a zero accumulator), FP64 beyond
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          if (!((m >> b) & 1)) continue;
-          f4 fb[2][2];
-#pragma unroll
-          for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh)
-              fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + (16 * t + m16) * kSP +
-                                                        4 * ((2 * g + hh) ^ (m16 & 7)));
-          // FP32 sums of 32 points each (the first MFMA takes a zero accumulator), FP64 beyond
-#pragma unroll
-          for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-            for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-              for (int tj = 0; tj < 2; ++tj)
-                acc[ti][2 * b + tj] = M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3],
-                                             kk == 0 ? zero : acc[ti][2 * b + tj]);
+        for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
           for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
             for (int tj = 0; tj < 2; ++tj)
+              acc[ti][2 * a + tj] = M::mma(fa[ti][kk >> 2][kk & 3], fb[tj][kk >> 2][kk & 3],
+                                           kk == 0 ? zero : acc[ti][2 * a + tj]);
 #pragma unroll
-              for (int v = 0; v < 4; ++v) dacc[ti][2 * b + tj][v] += double(acc[ti][2 * b + tj][v]);
-        }
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dacc[ti][2 * a + tj][v] += double(acc[ti][2 * a + tj][v]);
       }
     }
     __syncthreads();
@@ -1227,16 +1226,17 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
   }
   double *out = A.vpart + size_t(item) * (128 * 128);
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    if (diag && b == ws) continue;           // written by k_vdiag
+  for (int a = 0; a < 4; ++a) {
+    const int b = (ws - a) & 3;
+    if (diag && a == b) continue;           // written by k_vdiag
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = 32 * ws + 16 * ti + M::row(v, l), col = 32 * b + 16 * tj + m16;
-          out[row * 128 + col] = dacc[ti][2 * b + tj][v];
+          const int row = 32 * a + 16 * ti + M::row(v, l), col = 32 * b + 16 * tj + m16;
+          out[row * 128 + col] = dacc[ti][2 * a + tj][v];
         }
   }
   if (tid == 0) A.vflag[item] = 1;
@@ -1245,7 +1245,8 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
   });
 }
 
-// FP64 operands: the 4-wave Vxc kernel of k_vgemm_f32 on v_mfma_f64_16x16x4f64 (same items), with 16-point sub-steps so that a ring slot (4 Phi slabs and 4 Z slabs of 32 x 16) stays
+// FP64 operands: the 4-wave Vxc kernel of k_vgemm_f32 on v_mfma_f64_16x16x4f64 (same items and pair
+// ownership), with 16-point sub-steps so that a ring slot (4 Phi slabs and 4 Z slabs of 32 x 16) stays
 // 32 KB; MFMA step kk takes point 4 (l / 16) + kk of the sub-step.  With `accumulate` set, an item whose
 // partial an earlier launch wrote adds to it (the meta-GGA term).
 __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
@@ -1320,34 +1321,29 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
       wait_vm_lds<0>();
       wg_barrier();
       if (st + 1 < nst) issue(st + 1);
-      const int m = (__builtin_amdgcn_readfirstlane(s_m[st / kNS]) >> (4 * ws)) & 15;
-      if (m) {
-        const double *sl = ring + (st & 1) * kSlot;
-        d2 fa[2][2];
+      const int m = __builtin_amdgcn_readfirstlane(s_m[st / kNS]);
+      const double *sl = ring + (st & 1) * kSlot;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        // pair a of this wave: row tile a, column tile b = (w - a) mod 4; accumulators 2a, 2a + 1
+        const int b = (ws - a) & 3;
+        if (!((m >> (4 * a + b)) & 1)) continue;
+        d2 fa[2][2], fb[2][2];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-          for (int hh = 0; hh < 2; ++hh)
-            fa[t][hh] = *reinterpret_cast<const d2 *>(sl + ws * kSlab + (16 * t + m16) * kSP +
-                                                      2 * ((2 * g + hh) ^ (m16 & 7)));
+          for (int hh = 0; hh < 2; ++hh) {
+            const int off = (16 * t + m16) * kSP + 2 * ((2 * g + hh) ^ (m16 & 7));
+            fa[t][hh] = *reinterpret_cast<const d2 *>(sl + a * kSlab + off);
+            fb[t][hh] = *reinterpret_cast<const d2 *>(sl + (4 + b) * kSlab + off);
+          }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          if (!((m >> b) & 1)) continue;
-          d2 fb[2][2];
+        for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-          for (int t = 0; t < 2; ++t)
+          for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh)
-              fb[t][hh] = *reinterpret_cast<const d2 *>(sl + (4 + b) * kSlab + (16 * t + m16) * kSP +
-                                                        2 * ((2 * g + hh) ^ (m16 & 7)));
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-              for (int tj = 0; tj < 2; ++tj)
-                acc[ti][2 * b + tj] = M::mma(fa[ti][kk >> 1][kk & 1], fb[tj][kk >> 1][kk & 1], acc[ti][2 * b + tj]);
-        }
+            for (int tj = 0; tj < 2; ++tj)
+              acc[ti][2 * a + tj] = M::mma(fa[ti][kk >> 1][kk & 1], fb[tj][kk >> 1][kk & 1], acc[ti][2 * a + tj]);
       }
     }
     __syncthreads();
@@ -1358,15 +1354,19 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
   }
   double *out = A.vpart + size_t(item) * (128 * 128);
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int a = 0; a < 4; ++a) {
+    const int b = (ws - a) & 3;
 #pragma unroll
-    for (int tj = 0; tj < 8; ++tj)
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 32 * ws + 16 * ti + M::row(v, l), col = 16 * tj + m16;
-        const double val = acc[ti][tj][v];
-        out[row * 128 + col] = prev ? out[row * 128 + col] + val : val;
-      }
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 32 * a + 16 * ti + M::row(v, l), col = 32 * b + 16 * tj + m16;
+          const double val = acc[ti][2 * a + tj][v];
+          out[row * 128 + col] = prev ? out[row * 128 + col] + val : val;
+        }
+  }
   if (tid == 0) A.vflag[item] = 1;
   double pd = wave_sum(double(pairs));
   if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
@@ -1529,7 +1529,8 @@ __global__ __launch_bounds__(NT) void k_esum(const MolDev *mol, const double *__
 // when not NULL); which = 1: Q^a into Aout.
 __global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev st, int64_t ret0,
                                              const double *__restrict__ coef, int ax, int which,
-                                             double *__restrict__ Aout, double *__restrict__ Wout) {
+                                             double *__restrict__ Aout, double *__restrict__ Wout,
+                                             double *__restrict__ Amax, double *__restrict__ Wmax) {
   const int64_t k = ret0 + blockIdx.x;
   const int j = threadIdx.x;
   const int p = st.ret_p[k];
@@ -1540,11 +1541,31 @@ __global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev s
   const size_t o = size_t(blockIdx.x) * (kD * kG) + j;
   // second-derivative slots (xx xy xz yy yz zz) of row ax
   const int h0 = ax == 0 ? 0 : (ax == 1 ? 1 : 2), h1 = ax == 0 ? 1 : (ax == 1 ? 3 : 4), h2 = ax == 0 ? 2 : (ax == 1 ? 4 : 5);
+  double am = 0.0, wm = 0.0;
   for (int a = 0; a < kD; ++a) {
     double v, gr[3], h[6];
     eval_ao_hess(B, p * kD + a, x, y, z, v, gr, h);
-    Aout[o + a * kG] = which == 0 ? gr[ax] : c1 * h[h0] + c2 * h[h1] + c3 * h[h2];
-    if (Wout) Wout[o + a * kG] = c0 * v + c1 * gr[0] + c2 * gr[1] + c3 * gr[2];
+    const double av = which == 0 ? gr[ax] : c1 * h[h0] + c2 * h[h1] + c3 * h[h2];
+    Aout[o + a * kG] = av;
+    am = fmax(am, fabs(av));
+    if (Wout) {
+      const double wv = c0 * v + c1 * gr[0] + c2 * gr[1] + c3 * gr[2];
+      Wout[o + a * kG] = wv;
+      wm = fmax(wm, fabs(wv));
+    }
+  }
+  // the tile's max |A| (and max |W|) for the products' pair filter
+  __shared__ double s_m[2][2];
+  am = wave_max(am);
+  wm = wave_max(wm);
+  if ((j & 63) == 0) {
+    s_m[j >> 6][0] = am;
+    s_m[j >> 6][1] = wm;
+  }
+  __syncthreads();
+  if (j == 0 && Amax) {
+    Amax[blockIdx.x] = fmax(s_m[0][0], s_m[1][0]);
+    if (Wout) Wmax[blockIdx.x] = fmax(s_m[0][1], s_m[1][1]);
   }
 }
 
@@ -1632,7 +1653,8 @@ void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
         ta.t_d = 0.0;
         ta.counters = E.counters + 4;
         for (int a = 0; a < 3; ++a) {
-          k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr);
+          k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr, nullptr,
+                                      nullptr);
           ta.part = E.tpart[a];
           k_xgemm_f64<true><<<gx, NTX4, 0, s>>>(ta);
         }
@@ -1775,7 +1797,8 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
           tv.accumulate = 1;
           tv.counters = E.counters + 4;
           for (int a = 0; a < 3; ++a) {
-            k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr);
+            k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr, nullptr,
+                                      nullptr);
             k_tscale<<<nret, kG, 0, s>>>(P.st, C.ret0, E.ctau, E.tdphi, E.tB);
             k_vgemm_f64<<<gv, NTV4, 0, s>>>(tv);
           }
@@ -1821,19 +1844,25 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
 // Nuclear gradient of E_xc with the grid held fixed (FP64 plans of one molecule):
 //   dE/dR_Aa = -2 sum_{mu on A} sum_nu D_{mu nu} K^a_{mu nu},  K^a = (d_a Phi) W^T + Q^a Phi^T,
 //   W = c0 Phi + sum_b c_b d_b Phi,  Q^a = sum_b c_b d_a d_b Phi,  c0 = w v_rho,  c_b = 2 w v_sigma d_b rho.
-// The products run on k_vgemm_f64 over the Vxc work items, tile pairs (p, q) executing at block r when
-// (p, r), (q, r) are retained and a_pq >= t_b; each item's partial is contracted with D at once.
+// The products run on k_vgemm_f64 over the Vxc work items, tile pairs (p, q) of a product A B^T executing
+// at block r when (p, r), (q, r) are retained, a_pq >= t_b and a_pq max|A_pr| max|B_qr| >= t_d; each
+// item's partial is contracted with D at once.
 // LDA plans hold the chunk pairs pc <= qc only: there the pairs pc < qc also run the product with
 // its operands exchanged, W (d_a Phi)^T = (K^a)^T for the transposed chunk pair, contracted along columns.
 // ------------------------------------------------------------------------------------------------
 
-// One workgroup per grid block of the chunk: the executable tile pairs of the gradient products as
-// 16-bit masks per (row chunk, column chunk) pair: (p, r), (q, r) retained and a_pq >= t_b.  skip_diag:
-// no pair of a diagonal chunk pair (the exchanged-operand pass of LDA plans).
-__global__ __launch_bounds__(NT) void k_gmask(VMaskArgs A, const double *__restrict__ amax, int skip_diag) {
+// One workgroup per grid block of the chunk: the executable tile pairs of a gradient product A B^T as
+// 16-bit masks per (row chunk, column chunk) pair: (p, r), (q, r) retained, a_pq >= t_b and the bound of
+// the triple's D-contracted contribution a_pq max|A_pr| max|B_qr| >= t_d (the pair filter of eq.
+// block_pair_filter for the three factors; mA, mB: tile maxima indexed by retained tile - ret0).
+// skip_diag: no pair of a diagonal chunk pair (the exchanged-operand pass of LDA plans).
+__global__ __launch_bounds__(NT) void k_gmask(VMaskArgs A, const double *__restrict__ amax, int skip_diag,
+                                             const double *__restrict__ mA, const double *__restrict__ mB,
+                                             int64_t ret0) {
   const int64_t r = A.blk0 + blockIdx.x;
   const MolDev mo = A.st.mol[A.st.blk_mol[r]];
   const int *ci = A.cinfo + A.cioff[r];
+  const int64_t k0 = A.st.blk_off[r] - ret0;
   unsigned short *out = A.vmask + (A.vmoff[r] - A.vm_base);
   for (int pr = threadIdx.x; pr < mo.npairs; pr += NT) {
     const int pc = A.pair_info[3 * (mo.pair0 + pr)], qc = A.pair_info[3 * (mo.pair0 + pr) + 1];
@@ -1843,11 +1872,13 @@ __global__ __launch_bounds__(NT) void k_gmask(VMaskArgs A, const double *__restr
 #pragma unroll
       for (int ww = 0; ww < 4; ++ww) {
         if (!((ip >> ww) & 1)) continue;
+        const double ma = mA[k0 + tile_pos(ip, ww)];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           if (!((iq >> jj) & 1)) continue;
           const size_t t = size_t(mo.dt0) + size_t(4 * pc + ww) * mo.nt + (4 * qc + jj);
-          if (amax[t] >= A.t_b) mask |= 1 << (4 * ww + jj);
+          const double a = amax[t];
+          if (a >= A.t_b && a * ma * mB[k0 + tile_pos(iq, jj)] >= A.t_d) mask |= 1 << (4 * ww + jj);
         }
       }
     }
@@ -1938,21 +1969,25 @@ hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
     x_stage<double, 0>(P, ci, s, none);
     if (nret == 0 || nvit == 0) continue;
     const int64_t gv = 8 * P.vq.maxlen_h[ci];
-    auto product = [&](const void *opA, const void *opB, int skip_diag, int mode, int slot) {
-      k_gmask<<<nblk, NT, 0, s>>>(m_args(P, ci), E.amax, skip_diag);
+    const double *Am = P.grad_ws.gAmax, *Wm = P.grad_ws.gWmax, *Pm = P.st.bphi + C.ret0;   // tile maxima
+    auto product = [&](const void *opA, const void *opB, const double *mA, const double *mB, int skip_diag,
+                       int mode, int slot) {
+      k_gmask<<<nblk, NT, 0, s>>>(m_args(P, ci), E.amax, skip_diag, mA, mB, C.ret0);
       k_vgemm_f64<<<gv, NTV4, 0, s>>>(v_args(P, ci, opA, opB));
       k_gcontract<<<nvit, kG, 0, s>>>(P.items, C.vit0, P.st.mol, P.pair_info, E.vflag, E.vpart, Dt, mode, slot,
                                       P.grad_ws.gitem);
     };
     for (int ax = 0; ax < 3; ++ax) {
       k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 0, A,
-                                  ax == 0 ? static_cast<double *>(E.zws) : nullptr);
-      product(A, E.zws, 0, 0, 2 * ax);              // (d_a Phi) W^T
+                                  ax == 0 ? static_cast<double *>(E.zws) : nullptr, P.grad_ws.gAmax,
+                                  P.grad_ws.gWmax);
+      product(A, E.zws, Am, Wm, 0, 0, 2 * ax);              // (d_a Phi) W^T
       if (P.gga) {
-        k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 1, A, nullptr);
-        product(A, E.phi, 0, 0, 2 * ax + 1);        // Q^a Phi^T
+        k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 1, A, nullptr, P.grad_ws.gAmax,
+                                    nullptr);
+        product(A, E.phi, Am, Pm, 0, 0, 2 * ax + 1);        // Q^a Phi^T
       } else {
-        product(E.zws, A, 1, 1, 2 * ax + 1);        // W (d_a Phi)^T of the pairs pc < qc
+        product(E.zws, A, Wm, Am, 1, 1, 2 * ax + 1);        // W (d_a Phi)^T of the pairs pc < qc
       }
     }
   }

@@ -203,6 +203,8 @@ struct Plan {
   // nuclear gradient (kldi_eval_grad): workspaces of the current schedule, allocated on first use
   struct GradWs {
     double *gA = nullptr;     // [max chunk retained tiles * 4096] operand of the gradient products
+    double *gAmax = nullptr;  // [max chunk retained tiles] max |gA| of each tile
+    double *gWmax = nullptr;  // [max chunk retained tiles] max |W| of each tile (W in the Z workspace)
     double *gitem = nullptr;  // [n_items][6][128] per-item contracted partials
     double *gao = nullptr;    // [3][nc * 128] per-AO sums
   } grad_ws;

@@ -19,16 +19,17 @@ def Plan():
     return Plan
 
 
-def _grad(Plan, p, xc, **kw):
+def _grad(Plan, p, xc, with_count=False, **kw):
     plan = Plan.from_problem(p, xc=xc, prec="fp64", **kw)
     D = torch.from_numpy(p.D).cuda()
     exc = torch.empty(1, dtype=torch.float64, device="cuda")
     g = plan.grad(D, exc=exc).cpu().numpy()
+    n_prod = plan.check()["n_pairs_v"]        # tile triples of the gradient products
     _, e, _ = plan.eval(D, vxc=False)
     torch.cuda.synchronize()
     assert float(exc.item()) == float(e.item())
     plan.close()
-    return g
+    return (g, n_prod) if with_count else g
 
 
 @pytest.mark.parametrize("xc", ["lda", "pbe", "pbe_x"])
@@ -37,10 +38,30 @@ def test_tiny_gradient_matches_blocked_oracle(Plan, xc, shape):
     n_atoms, n_rad, n_ang, n_occ, seed = shape
     p = synth.tiny_problem(n_atoms=n_atoms, n_rad=n_rad, n_ang=n_ang, n_occ=n_occ, xc=xc, seed=seed, box_A=4.0)
     print("case: tiny gradient %s xc=%s" % (p.name, xc), flush=True)
-    ref = og.exc_gradient_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc,
-                                  t_b=1e-10)
-    g = _grad(Plan, p, xc)
-    print("  max |dg| %.2e of max |g| %.2e" % (np.abs(g - ref).max(), np.abs(ref).max()), flush=True)
+    ref, n_ref = og.exc_gradient_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D,
+                                         xc, t_b=1e-10, return_count=True)
+    g, n = _grad(Plan, p, xc, with_count=True)
+    print("  max |dg| %.2e of max |g| %.2e, %d product triples" % (np.abs(g - ref).max(), np.abs(ref).max(), n),
+          flush=True)
+    assert np.abs(g - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert n == n_ref
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_gradient_pair_filter_against_blocked_oracle(Plan, xc):
+    """A pair threshold large enough to drop product triples on a small molecule (t_d = 1e-6 with t_b =
+    1e-10): the same executed triples as the oracle's filter a_pq max|A_pr| max|B_qr| >= t_d, and the same
+    gradient to 1e-12."""
+    p = synth.tiny_problem(n_atoms=5, n_rad=14, n_ang=38, n_occ=5, xc=xc, seed=47, box_A=5.0)
+    print("case: gradient pair filter %s xc=%s" % (p.name, xc), flush=True)
+    ref, n_ref = og.exc_gradient_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D,
+                                         xc, t_b=1e-10, t_d=1e-6, return_count=True)
+    _, n_all = og.exc_gradient_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D,
+                                       xc, t_b=1e-10, t_d=1e-6, t_grad=0.0, return_count=True)
+    g, n = _grad(Plan, p, xc, with_count=True, t_b=1e-10, t_d=1e-6)
+    print("  %d of %d product triples, max |dg| %.2e" % (n, n_all, np.abs(g - ref).max()), flush=True)
+    assert n_ref < n_all
+    assert n == n_ref
     assert np.abs(g - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
 
 

@@ -60,3 +60,20 @@ def test_blocked_gradient_without_screening_equals_dense(xc):
                                  t_b=1e-10)
     print(xc, "screening at 1e-10 moves the gradient by %.2e" % np.abs(gs - g).max())
     assert np.abs(gs - g).max() <= 1e-6 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_gradient_pair_filter_drops_only_bounded_triples(xc):
+    """The gradient products' pair filter a_pq max|A_pr| max|B_qr| >= t: raising t drops triples, and each
+    dropped triple moves the D-contracted sum by at most d^2 G times its bound (< t), so the gradient moves
+    by at most 2 n_dropped d^2 G t (d = 32 AOs, G = 128 points); t = 0 keeps every triple."""
+    p = synth.tiny_problem(n_atoms=4, n_rad=12, n_ang=26, n_occ=3, xc=xc, seed=12, box_A=4.0)
+    args = (p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc)
+    g0, n0 = og.exc_gradient_blocked(*args, t_b=1e-10, t_d=1e-10, t_grad=0.0, return_count=True)
+    for t in (1e-8, 1e-6, 1e-4):
+        g1, n1 = og.exc_gradient_blocked(*args, t_b=1e-10, t_d=1e-10, t_grad=t, return_count=True)
+        bound = 2.0 * (n0 - n1) * 32 * 32 * 128 * t
+        print(xc, "t %.0e: %d of %d triples, |dg| %.2e <= %.2e" % (t, n1, n0, np.abs(g1 - g0).max(), bound))
+        assert n1 <= n0
+        assert np.abs(g1 - g0).max() <= bound
+    assert n1 < n0        # the largest t drops triples
