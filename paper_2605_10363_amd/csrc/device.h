@@ -90,22 +90,47 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *ro(const T
 }
 
 // Calls emit(a, value, gx, gy, gz) for every AO a (local row 0..31) of tile p at (x, y, z).
+// The shell data come from the packed per-shell records (wide scalar loads, the next shell's issued before
+// this shell's arithmetic): the loop waits on memory once per shell instead of once per
+// table and primitive.
+struct ShRec {
+  double v[kShRec];
+};
+__device__ __forceinline__ ShRec load_shrec(const BasisDev &B, int s) {
+  const auto r = ro(B.shrec) + size_t(s) * kShRec;
+  ShRec o;
+#pragma unroll
+  for (int i = 0; i < kShRec; ++i) o.v[i] = r[i];
+  return o;
+}
 template <bool GRAD, class F>
 __device__ __forceinline__ void for_tile_aos(const BasisDev &B, int p, double x, double y, double z, F &&emit) {
-  const auto tile_sh = ro(B.tile_sh), sh_prim = ro(B.sh_prim), sh_l = ro(B.sh_l), sh_ao0 = ro(B.sh_ao0);
-  const auto sh_xyz = ro(B.sh_xyz), pexp = ro(B.pexp), pcoef = ro(B.pcoef);
+  const auto tile_sh = ro(B.tile_sh);
+  const auto pexp = ro(B.pexp), pcoef = ro(B.pcoef);
   const int s0 = tile_sh[2 * p], s1 = tile_sh[2 * p + 1];
   const int a_lo = p * kD, a_hi = a_lo + kD;
+  ShRec nxt;
+  if (s0 < s1) nxt = load_shrec(B, s0);
   for (int s = s0; s < s1; ++s) {
-    const double dx = x - sh_xyz[3 * s], dy = y - sh_xyz[3 * s + 1], dz = z - sh_xyz[3 * s + 2];
+    const ShRec rc = nxt;
+    if (s + 1 < s1) nxt = load_shrec(B, s + 1);
+    const int32_t *w = reinterpret_cast<const int32_t *>(&rc.v[3]);
+    const int l = w[1] & 3, np = w[1] >> 2, ao0 = w[0], pb = w[2];
+    const double dx = x - rc.v[0], dy = y - rc.v[1], dz = z - rc.v[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
     double R = 0.0, R1 = 0.0;
-    for (int k = sh_prim[2 * s]; k < sh_prim[2 * s + 1]; ++k) {
+#pragma unroll
+    for (int k = 0; k < kShPrimIn; ++k) {
+      if (k >= np) break;
+      const double e = rc.v[6 + 2 * k] * exp(-rc.v[5 + 2 * k] * r2);
+      R += e;
+      if (GRAD) R1 -= 2.0 * rc.v[5 + 2 * k] * e;
+    }
+    for (int k = pb + kShPrimIn; k < pb + np; ++k) {
       const double e = pcoef[k] * exp(-pexp[k] * r2);
       R += e;
       if (GRAD) R1 -= 2.0 * pexp[k] * e;
     }
-    const int l = sh_l[s], ao0 = sh_ao0[s];
     // component c of the shell: angular factor A (N_rel included) and its derivatives; value A R,
     // gradient dA R + A (dx, dy, dz) R1, in AO order.
     auto put = [&](int c, double A, double ax, double ay, double az) {
@@ -169,24 +194,11 @@ __device__ __forceinline__ void eval_ao(const BasisDev &B, int ao, double x, dou
 // zero on padding rows.  With A the monomial (N_rel included), R = sum c e^{-a r^2}, R1 = sum (-2a) c
 // e^{-a r^2}, R2 = sum (2a)^2 c e^{-a r^2}:  d_a chi = A_a R + A d_a R1,
 // d_a d_b chi = A_ab R + A_a d_b R1 + A_b d_a R1 + A (delta_ab R1 + d_a d_b R2).
-__device__ __forceinline__ void eval_ao_hess(const BasisDev &B, int ao, double x, double y, double z, double &v,
-                                             double *g, double *h) {
-  v = 0.0;
-  for (int k = 0; k < 3; ++k) g[k] = 0.0;
-  for (int k = 0; k < 6; ++k) h[k] = 0.0;
-  const int s = B.ao_shell[ao];
-  if (s < 0) return;
-  const double d[3] = {x - B.sh_xyz[3 * s], y - B.sh_xyz[3 * s + 1], z - B.sh_xyz[3 * s + 2]};
-  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-  double R = 0.0, R1 = 0.0, R2 = 0.0;
-  for (int k = B.sh_prim[2 * s]; k < B.sh_prim[2 * s + 1]; ++k) {
-    const double a2 = 2.0 * B.pexp[k];
-    const double e = B.pcoef[k] * exp(-B.pexp[k] * r2);
-    R += e;
-    R1 -= a2 * e;
-    R2 += a2 * a2 * e;
-  }
-  const int cp = B.ao_comp[ao];
+// Value, gradient and Hessian (xx xy xz yy yz zz) of the cartesian component with powers cp = lx | ly << 2 |
+// lz << 4 (N_rel included) from the shell's radial sums R = sum c e^(-a r2), R1 = sum -2a c e^(-a r2),
+// R2 = sum 4a^2 c e^(-a r2) at offset d from its centre.
+__device__ __forceinline__ void ao_hess_from_radial(int cp, const double *d, double R, double R1, double R2, double &v,
+                                                    double *g, double *h) {
   const int l[3] = {cp & 3, (cp >> 2) & 3, (cp >> 4) & 3};
   const double nr = ((l[0] == 1) + (l[1] == 1) + (l[2] == 1) == 2) ? kSqrt3 : 1.0;
   // t^l and its first two derivatives per axis
@@ -217,6 +229,70 @@ __device__ __forceinline__ void eval_ao_hess(const BasisDev &B, int ao, double x
       }
       h[k] = Aab * R + Aa[a] * d[b] * R1 + Aa[b] * d[a] * R1 + A * ((a == b ? R1 : 0.0) + d[a] * d[b] * R2);
     }
+}
+
+__device__ __forceinline__ void eval_ao_hess(const BasisDev &B, int ao, double x, double y, double z, double &v,
+                                             double *g, double *h) {
+  v = 0.0;
+  for (int k = 0; k < 3; ++k) g[k] = 0.0;
+  for (int k = 0; k < 6; ++k) h[k] = 0.0;
+  const int s = B.ao_shell[ao];
+  if (s < 0) return;
+  const double d[3] = {x - B.sh_xyz[3 * s], y - B.sh_xyz[3 * s + 1], z - B.sh_xyz[3 * s + 2]};
+  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double R = 0.0, R1 = 0.0, R2 = 0.0;
+  for (int k = B.sh_prim[2 * s]; k < B.sh_prim[2 * s + 1]; ++k) {
+    const double a2 = 2.0 * B.pexp[k];
+    const double e = B.pcoef[k] * exp(-B.pexp[k] * r2);
+    R += e;
+    R1 -= a2 * e;
+    R2 += a2 * a2 * e;
+  }
+  ao_hess_from_radial(B.ao_comp[ao], d, R, R1, R2, v, g, h);
+}
+
+// Calls emit(a, value, gradient[3], hessian[6]) for every AO a (local row 0..31) of tile p at (x, y, z),
+// as eval_ao_hess computes them (the same arithmetic), with the radial sums formed once per shell from the
+// packed shell records.
+template <class F>
+__device__ __forceinline__ void for_tile_aos_hess(const BasisDev &B, int p, double x, double y, double z, F &&emit) {
+  const auto tile_sh = ro(B.tile_sh);
+  const auto pexp = ro(B.pexp), pcoef = ro(B.pcoef);
+  const auto ao_comp = ro(B.ao_comp);
+  const int s0 = tile_sh[2 * p], s1 = tile_sh[2 * p + 1];
+  const int a_lo = p * kD, a_hi = a_lo + kD;
+  for (int s = s0; s < s1; ++s) {
+    const ShRec rc = load_shrec(B, s);
+    const int32_t *w = reinterpret_cast<const int32_t *>(&rc.v[3]);
+    const int l = w[1] & 3, np = w[1] >> 2, ao0 = w[0], pb = w[2];
+    const double d[3] = {x - rc.v[0], y - rc.v[1], z - rc.v[2]};
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double R = 0.0, R1 = 0.0, R2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kShPrimIn; ++k) {
+      if (k >= np) break;
+      const double a2 = 2.0 * rc.v[5 + 2 * k];
+      const double e = rc.v[6 + 2 * k] * exp(-rc.v[5 + 2 * k] * r2);
+      R += e;
+      R1 -= a2 * e;
+      R2 += a2 * a2 * e;
+    }
+    for (int k = pb + kShPrimIn; k < pb + np; ++k) {
+      const double a2 = 2.0 * pexp[k];
+      const double e = pcoef[k] * exp(-pexp[k] * r2);
+      R += e;
+      R1 -= a2 * e;
+      R2 += a2 * a2 * e;
+    }
+    const int nc = (l + 1) * (l + 2) / 2;
+    for (int c = 0; c < nc; ++c) {
+      const int ao = ao0 + c;
+      if (ao < a_lo || ao >= a_hi) continue;
+      double v, g[3], h[6];
+      ao_hess_from_radial(ao_comp[ao], d, R, R1, R2, v, g, h);
+      emit(ao - a_lo, v, g, h);
+    }
+  }
 }
 
 // ------------------------------------------------------------------------------------------------

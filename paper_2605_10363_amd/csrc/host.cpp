@@ -865,6 +865,24 @@ void build_plan(Plan &P, int n_mol, const kldi_basis *bs, const kldi_grid *gs, c
   B.ao_comp = dev_upload(P, ao_comp);
   B.tile_sh = dev_upload(P, tile_sh);
   B.tile_nv = dev_upload(P, tile_nv);
+  {
+    const size_t ns = sh_l.size();
+    std::vector<double> rec(ns * kShRec, 0.0);
+    for (size_t s = 0; s < ns; ++s) {
+      double *r = rec.data() + s * kShRec;
+      r[0] = sh_xyz[3 * s];
+      r[1] = sh_xyz[3 * s + 1];
+      r[2] = sh_xyz[3 * s + 2];
+      const int p0 = sh_prim[2 * s], np = sh_prim[2 * s + 1] - p0;
+      const int32_t w[4] = {sh_ao0[s], sh_l[s] | (np << 2), p0, 0};
+      std::memcpy(r + 3, w, sizeof(w));
+      for (int k = 0; k < std::min(np, kShPrimIn); ++k) {
+        r[5 + 2 * k] = pexp[size_t(p0 + k)];
+        r[6 + 2 * k] = pcoef[size_t(p0 + k)];
+      }
+    }
+    B.shrec = dev_upload(P, rec);
+  }
   GridDev &Gd = P.grid;
   Gd.x = dev_upload(P, px);
   Gd.y = dev_upload(P, py);

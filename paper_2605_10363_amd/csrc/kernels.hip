@@ -1542,9 +1542,11 @@ __global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev s
   // second-derivative slots (xx xy xz yy yz zz) of row ax
   const int h0 = ax == 0 ? 0 : (ax == 1 ? 1 : 2), h1 = ax == 0 ? 1 : (ax == 1 ? 3 : 4), h2 = ax == 0 ? 2 : (ax == 1 ? 4 : 5);
   double am = 0.0, wm = 0.0;
-  for (int a = 0; a < kD; ++a) {
-    double v, gr[3], h[6];
-    eval_ao_hess(B, p * kD + a, x, y, z, v, gr, h);
+  for (int a = B.tile_nv[p]; a < kD; ++a) {   // padding rows
+    Aout[o + a * kG] = 0.0;
+    if (Wout) Wout[o + a * kG] = 0.0;
+  }
+  for_tile_aos_hess(B, p, x, y, z, [&](int a, double v, const double *gr, const double *h) {
     const double av = which == 0 ? gr[ax] : c1 * h[h0] + c2 * h[h1] + c3 * h[h2];
     Aout[o + a * kG] = av;
     am = fmax(am, fabs(av));
@@ -1553,7 +1555,7 @@ __global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev s
       Wout[o + a * kG] = wv;
       wm = fmax(wm, fabs(wv));
     }
-  }
+  });
   // the tile's max |A| (and max |W|) for the products' pair filter
   __shared__ double s_m[2][2];
   am = wave_max(am);
@@ -1924,18 +1926,24 @@ __global__ __launch_bounds__(kG) void k_greduce(const MolDev *__restrict__ mol, 
                                                const double *__restrict__ gitem, int lda, double *__restrict__ gao,
                                                int ld) {
   const MolDev mo = mol[0];
-  const int c = blockIdx.x, i = threadIdx.x;
+  const int c = blockIdx.x, i = threadIdx.x, nc = mo.nc;
+  // the pairs of chunk c in pair order: (pc, c) for pc < c (LDA plans, which hold pc <= qc: its columns),
+  // then (c, qc) (its rows); pair index pc nc + qc (GGA) or pc nc - pc (pc - 1) / 2 + (qc - pc) (LDA)
   for (int a = 0; a < 3; ++a) {
     double s = 0.0;
-    for (int pr = mo.pair0; pr < mo.pair0 + mo.npairs; ++pr) {
-      const int pc = pair_info[3 * pr], qc = pair_info[3 * pr + 1];
-      const bool rows = pc == c, cols = lda && qc == c && pc != c;
-      if (!rows && !cols) continue;
+    if (lda) {
+      for (int pc = 0; pc < c; ++pc) {
+        const int pr = mo.pair0 + pc * nc - pc * (pc - 1) / 2 + (c - pc);
+        for (int k = pair_ptr[pr]; k < pair_ptr[pr + 1]; ++k)
+          s += gitem[size_t(pair_items[k]) * 6 * 128 + (2 * a + 1) * 128 + i];
+      }
+    }
+    for (int qc = lda ? c : 0; qc < nc; ++qc) {
+      const int pr = mo.pair0 + (lda ? c * nc - c * (c - 1) / 2 + (qc - c) : c * nc + qc);
       for (int k = pair_ptr[pr]; k < pair_ptr[pr + 1]; ++k) {
         const double *gi = gitem + size_t(pair_items[k]) * 6 * 128 + i;
-        if (rows) s += gi[(2 * a) * 128];
-        if (rows && !lda) s += gi[(2 * a + 1) * 128];
-        if (cols) s += gi[(2 * a + 1) * 128];
+        s += gi[(2 * a) * 128];
+        if (!lda) s += gi[(2 * a + 1) * 128];
       }
     }
     gao[size_t(a) * ld + size_t(c) * 128 + i] = s;

@@ -79,7 +79,13 @@ struct BasisDev {
   const int *ao_comp;      // [n_ao_pad] cartesian powers packed lx | ly<<2 | lz<<4
   const int *tile_sh;      // [n_tiles*2] shells overlapping each tile
   const int *tile_nv;      // [n_tiles] AOs of each tile (32 but on a molecule's last tile)
+  // [n_shells * kShRec] the same shell data packed per shell (one 96-byte record, read with wide scalar
+  // loads): centre x y z; int32 first internal AO and l | n_prim << 2; int32 first primitive; the first
+  // kShPrimIn primitives as (exponent, coefficient); further primitives from pexp / pcoef
+  const double *shrec;
 };
+constexpr int kShRec = 11;      // doubles per shell record
+constexpr int kShPrimIn = 3;    // primitives held in a shell record
 
 // Device view of the reordered, padded grid.
 struct GridDev {
