@@ -1902,6 +1902,7 @@ __global__ __launch_bounds__(kG) void k_gcontract(const VItem *__restrict__ item
   const MolDev mo = mol[pair_info[3 * it.pair + 2]];
   const int i = threadIdx.x;
   double s = 0.0;
+  __shared__ double s_pd[128][33];   // row sums: P .* D of 32 columns, rows padded against bank conflicts
   if (vflag[item]) {
     const double *Pp = vpart + size_t(item) * 16384;
     auto d = [&](int row, int col) {   // D of AO row of chunk pc, AO col of chunk qc
@@ -1909,10 +1910,21 @@ __global__ __launch_bounds__(kG) void k_gcontract(const VItem *__restrict__ item
       if (p >= mo.nt || q >= mo.nt) return 0.0;
       return Dt[(size_t(mo.dt0) + size_t(p) * mo.nt + q) * 1024 + (row & 31) * 32 + (col & 31)];
     };
-    if (mode == 0)
-      for (int j = 0; j < 128; ++j) s += d(i, j) * Pp[i * 128 + j];
-    else
+    if (mode == 0) {
+      // 32 columns at a time: the products are formed with coalesced reads (a row of 32 columns per 32
+      // threads), then each thread sums its row in column order
+      for (int jb = 0; jb < 128; jb += 32) {
+        for (int e = i; e < 128 * 32; e += 128) {
+          const int row = e >> 5, col = jb + (e & 31);
+          s_pd[row][e & 31] = d(row, col) * Pp[row * 128 + col];
+        }
+        __syncthreads();
+        for (int c = 0; c < 32; ++c) s += s_pd[i][c];
+        __syncthreads();
+      }
+    } else {
       for (int j = 0; j < 128; ++j) s += d(j, i) * Pp[j * 128 + i];
+    }
   }
   gitem[(size_t(item) * 6 + slot) * 128 + i] = s;
 }
