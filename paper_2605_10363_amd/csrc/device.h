@@ -103,6 +103,18 @@ __device__ __forceinline__ ShRec load_shrec(const BasisDev &B, int s) {
   for (int i = 0; i < kShRec; ++i) o.v[i] = r[i];
   return o;
 }
+// e^(-a r2) of one primitive, or 0 where a r2 >= kExpCut: such a term is below e^-70 (4e-31) of its
+// coefficient, under FP64 resolution of every basis value and density the screening and the functional
+// act on (the density floor is 1e-14).  The test is per lane, so a point's value does not depend on its
+// wave; the exponential is skipped where every lane of the wave is that far from the primitive (tight
+// primitives at the distant points of a retained tile).
+constexpr double kExpCut = 70.0;
+__device__ __forceinline__ double prim_exp(double a, double r2) {
+  const double q = a * r2;
+  double e = 0.0;
+  if (q < kExpCut) e = exp(-q);
+  return e;
+}
 template <bool GRAD, class F>
 __device__ __forceinline__ void for_tile_aos(const BasisDev &B, int p, double x, double y, double z, F &&emit) {
   const auto tile_sh = ro(B.tile_sh);
@@ -122,12 +134,12 @@ __device__ __forceinline__ void for_tile_aos(const BasisDev &B, int p, double x,
 #pragma unroll
     for (int k = 0; k < kShPrimIn; ++k) {
       if (k >= np) break;
-      const double e = rc.v[6 + 2 * k] * exp(-rc.v[5 + 2 * k] * r2);
+      const double e = rc.v[6 + 2 * k] * prim_exp(rc.v[5 + 2 * k], r2);
       R += e;
       if (GRAD) R1 -= 2.0 * rc.v[5 + 2 * k] * e;
     }
     for (int k = pb + kShPrimIn; k < pb + np; ++k) {
-      const double e = pcoef[k] * exp(-pexp[k] * r2);
+      const double e = pcoef[k] * prim_exp(pexp[k], r2);
       R += e;
       if (GRAD) R1 -= 2.0 * pexp[k] * e;
     }
@@ -172,7 +184,7 @@ __device__ __forceinline__ void eval_ao(const BasisDev &B, int ao, double x, dou
   const double r2 = dx * dx + dy * dy + dz * dz;
   double R = 0.0, R1 = 0.0;
   for (int k = B.sh_prim[2 * s]; k < B.sh_prim[2 * s + 1]; ++k) {
-    const double e = B.pcoef[k] * exp(-B.pexp[k] * r2);
+    const double e = B.pcoef[k] * prim_exp(B.pexp[k], r2);
     R += e;
     R1 -= 2.0 * B.pexp[k] * e;
   }
@@ -243,7 +255,7 @@ __device__ __forceinline__ void eval_ao_hess(const BasisDev &B, int ao, double x
   double R = 0.0, R1 = 0.0, R2 = 0.0;
   for (int k = B.sh_prim[2 * s]; k < B.sh_prim[2 * s + 1]; ++k) {
     const double a2 = 2.0 * B.pexp[k];
-    const double e = B.pcoef[k] * exp(-B.pexp[k] * r2);
+    const double e = B.pcoef[k] * prim_exp(B.pexp[k], r2);
     R += e;
     R1 -= a2 * e;
     R2 += a2 * a2 * e;
@@ -272,14 +284,14 @@ __device__ __forceinline__ void for_tile_aos_hess(const BasisDev &B, int p, doub
     for (int k = 0; k < kShPrimIn; ++k) {
       if (k >= np) break;
       const double a2 = 2.0 * rc.v[5 + 2 * k];
-      const double e = rc.v[6 + 2 * k] * exp(-rc.v[5 + 2 * k] * r2);
+      const double e = rc.v[6 + 2 * k] * prim_exp(rc.v[5 + 2 * k], r2);
       R += e;
       R1 -= a2 * e;
       R2 += a2 * a2 * e;
     }
     for (int k = pb + kShPrimIn; k < pb + np; ++k) {
       const double a2 = 2.0 * pexp[k];
-      const double e = pcoef[k] * exp(-pexp[k] * r2);
+      const double e = pcoef[k] * prim_exp(pexp[k], r2);
       R += e;
       R1 -= a2 * e;
       R2 += a2 * a2 * e;

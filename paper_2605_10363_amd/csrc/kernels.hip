@@ -253,6 +253,13 @@ __device__ __forceinline__ void dma16(const void *src, void *lds_wave) {
   asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
                : "memory", "m0");
 }
+// Swizzle of the 16-byte units of a 128-byte LDS row i (32 rows to a tile slab): unit c of the row is
+// stored at c ^ swz(i).  The fragment reads take one unit of each of 16 consecutive rows per 16 lanes;
+// under this map the 16 units fall in 16 distinct 16-byte bank groups whether the LDS serves 8 lanes
+// over 32 banks or 16 lanes over 64 banks per cycle (c ^ (i & 7) left rows i and i + 8 in one group of
+// 64 banks, a two-way conflict on every read).  Rows i and i + 16 share a swizzle, so the reads of the
+// two 16-row halves of a slab differ by a constant offset.
+__device__ __forceinline__ int swz(int i) { return (i ^ ((i >> 3) & 1)) & 7; }
 // s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
 template <int N>
 __device__ __forceinline__ void wait_vm_lds() {
@@ -621,14 +628,14 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
   const int pa = __builtin_amdgcn_readfirstlane(s_p[min(4 * c + ws, np - 1)]);
   const float *Drow = Df + dtile(pa, mo.tile0) * (kD * kD);
   // entry e goes to slot e % 2: wave w copies D_(p_w, q) as [row i][k] with the 16-byte units of row i
-  // XOR-swizzled (unit c at c ^ (i & 7)), and quarter w of Phi_q as [k][point], global -> LDS directly
+  // XOR-swizzled (unit c at c ^ swz(i)), and quarter w of Phi_q as [k][point], global -> LDS directly
   auto issue = [&](int e) {
     float *dst = ring + (e & 1) * kEnt;
     const int q = __builtin_amdgcn_readfirstlane(s_q[e]);
     const float *src = Drow + size_t(q - mo.tile0) * (kD * kD);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+      const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ swz(i);
       dma16(src + i * kD + 4 * cu, dst + ws * (kD * kD) + 256 * m);
     }
     const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
@@ -661,7 +668,7 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
           a[ti][hh] = *reinterpret_cast<const f4 *>(se + ws * (kD * kD) + (16 * ti + m16) * kD +
-                                                    4 * ((2 * g + hh) ^ (m16 & 7)));
+                                                    4 * ((2 * g + hh) ^ swz(16 * ti + m16)));
       const float *sb = se + 4 * kD * kD + 4 * m16;
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
@@ -697,9 +704,11 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
 #pragma unroll
         for (int tj = 0; tj < 8; ++tj)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            Xw[(16 * ti + M::row(v, l)) * kG + 64 * (tj >> 2) + 4 * m16 + (tj & 3)] =
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * ti + M::row(v, l);
+            Xw[row * kG + 64 * (tj >> 2) + 4 * m16 + (tj & 3)] =
                 ti == 0 ? dacc[ti][tj][v] + double(acc[ti][tj][v]) : dacc[ti][tj][v];   // row 1: flushed
+          }
     }
     __syncthreads();
     const int slot = 4 * c + 2 * R + slot_w;
@@ -720,7 +729,8 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
       } else {
         const float *ph = phi + size_t(k0 + slot) * (kD * kG) + j;
         const unsigned short *pl = A.phil + size_t(k0 + slot - A.ret0) * (kD * kG) + j;
-        for (int a = 0; a < kD; ++a) s0 += (double(ph[a * kG]) + from_bf16(pl[a * kG])) * Xw[a * kG + j];
+        for (int a = 0; a < kD; ++a)
+          s0 += (double(ph[a * kG]) + from_bf16(pl[a * kG])) * Xw[a * kG + j];
       }
     }
     s_acc[slot_w][0][j] = s0;
@@ -744,7 +754,7 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f32(XArgs A) {
 }
 
 // FP64 operands: the 4-wave X kernel of k_xgemm_f32 on v_mfma_f64_16x16x4f64 (same items).  An FP64 entry (64 KB) is taken in two K halves of 16 values, each a ring slot of 32 KB
-// (4 D half-tiles [row i][k] with the 16-byte units of row i XOR-swizzled, unit c at c ^ (i & 7), and
+// (4 D half-tiles [row i][k] with the 16-byte units of row i XOR-swizzled, unit c at c ^ swz(i), and
 // half of Phi_q as [k][point]); MFMA step kk of a half takes k = 4 (l / 16) + kk, and output column c of
 // sub-tile tj is point 32 (tj / 2) + 2 c + tj % 2 (the 16 lanes of a row read 256 contiguous bytes per
 // 16-byte load).  The accumulators are FP64, so X needs no flush.
@@ -821,7 +831,7 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f64(XArgs A) {
     const double *src = Drow + size_t(q - mo.tile0) * (kD * kD) + kHalf * h;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+      const int tu = 64 * m + l, i = tu >> 3, cu = (tu & 7) ^ swz(i);
       dma16(src + i * kD + 2 * cu, dst + ws * (kD * kHalf) + 128 * m);
     }
     const int t = __builtin_amdgcn_readfirstlane(s_list[e] & 0xffff);
@@ -843,7 +853,7 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f64(XArgs A) {
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
           a[ti][hh] = *reinterpret_cast<const d2 *>(se + ws * (kD * kHalf) + (16 * ti + m16) * kHalf +
-                                                    2 * ((2 * g + hh) ^ (m16 & 7)));
+                                                    2 * ((2 * g + hh) ^ swz(16 * ti + m16)));
       const double *sb = se + 4 * kD * kHalf + 2 * m16;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
@@ -875,8 +885,10 @@ __global__ __launch_bounds__(NTX4, 2) void k_xgemm_f64(XArgs A) {
 #pragma unroll
         for (int tj = 0; tj < 8; ++tj)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            Xw[(16 * ti + M::row(v, l)) * kG + 32 * (tj >> 1) + 2 * m16 + (tj & 1)] = acc[ti][tj][v];
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * ti + M::row(v, l);
+            Xw[row * kG + 32 * (tj >> 1) + 2 * m16 + (tj & 1)] = acc[ti][tj][v];
+          }
     }
     __syncthreads();
     const int slot = 4 * c + 2 * R + slot_w;
@@ -1150,7 +1162,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
     any |= tot;
     // sub-step st = kNS e + sub: entry e of the compacted list, points kSP sub .. kSP sub + kSP - 1.  Slot
     // st % 2: slab a < 4 is Phi_(4pc+a), slab 4 + b is Z_(4qc+b), each [row i][point] with the 16-byte
-    // units of row i XOR-swizzled (unit c at c ^ (i & 7)); wave w copies slabs w and 4 + w, global -> LDS
+    // units of row i XOR-swizzled (unit c at c ^ swz(i)); wave w copies slabs w and 4 + w, global -> LDS
     // directly, one sub-step ahead, and only where the slab's tile has an executable pair.
     const int nst = kNS * tot;
     auto issue = [&](int st) {
@@ -1163,7 +1175,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
         const float *src = Pf + size_t(bo + tile_pos(info, ws)) * (kD * kG) + kSP * sub;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ swz(i);
           dma16(src + i * kG + 4 * cu, dst + ws * kSlab + 256 * k);
         }
       }
@@ -1172,7 +1184,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
         const float *src = Zf + size_t(bo + tile_pos(info, ws)) * (kD * kG) + kSP * sub;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ swz(i);
           dma16(src + i * kG + 4 * cu, dst + (4 + ws) * kSlab + 256 * k);
         }
       }
@@ -1197,7 +1209,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
         for (int t = 0; t < 2; ++t)
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh) {
-            const int off = (16 * t + m16) * kSP + 4 * ((2 * g + hh) ^ (m16 & 7));
+            const int off = (16 * t + m16) * kSP + 4 * ((2 * g + hh) ^ swz(16 * t + m16));
             fa[t][hh] = *reinterpret_cast<const f4 *>(sl + a * kSlab + off);
             fb[t][hh] = *reinterpret_cast<const f4 *>(sl + (4 + b) * kSlab + off);
           }
@@ -1302,7 +1314,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
         const double *src = Pd + size_t(bo + tile_pos(info, ws)) * (kD * kG) + kSP * sub;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ swz(i);
           dma16(src + i * kG + 2 * cu, dst + ws * kSlab + 128 * k);
         }
       }
@@ -1311,7 +1323,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
         const double *src = Zd + size_t(bo + tile_pos(info, ws)) * (kD * kG) + kSP * sub;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ (i & 7);
+          const int tu = 64 * k + l, i = tu >> 3, cu = (tu & 7) ^ swz(i);
           dma16(src + i * kG + 2 * cu, dst + (4 + ws) * kSlab + 128 * k);
         }
       }
@@ -1333,7 +1345,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
         for (int t = 0; t < 2; ++t)
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh) {
-            const int off = (16 * t + m16) * kSP + 2 * ((2 * g + hh) ^ (m16 & 7));
+            const int off = (16 * t + m16) * kSP + 2 * ((2 * g + hh) ^ swz(16 * t + m16));
             fa[t][hh] = *reinterpret_cast<const d2 *>(sl + a * kSlab + off);
             fb[t][hh] = *reinterpret_cast<const d2 *>(sl + (4 + b) * kSlab + off);
           }
