@@ -562,27 +562,33 @@ def main():
                 out["err_vs_oracle"]["%s_%s" % (tag, prec)] = {"E_xc": abs(r["E"] - g["E"]), "V_maxabs_sampled": dv}
 
     if args.config == 1 and not args.no_fp64:
-        # the nuclear gradient of E_xc with the grid held fixed (FP64 plans), beside the energy evaluation
-        plan = Plan.from_problem(p, prec="fp64", shell_order=so)
-        g = plan.grad(D)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        reps = max(2, args.steps // 2)
-        e0.record()
-        for _ in range(reps):
+        # the nuclear gradient of E_xc with the grid held fixed, on an FP64 plan and on an FP32 plan, beside the
+        # energy evaluation
+        grads = {}
+        for gprec in ("fp64", "fp32"):
+            plan = Plan.from_problem(p, prec=gprec, shell_order=so)
             g = plan.grad(D)
-        e1.record()
-        torch.cuda.synchronize()
-        gms = e0.elapsed_time(e1) / reps
-        gn = g.cpu().numpy()
-        log("fp64 gradient: %.3f ms, max |dE/dR| %.3e" % (gms, np.abs(gn).max()))
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = max(2, args.steps // 2)
+            e0.record()
+            for _ in range(reps):
+                g = plan.grad(D)
+            e1.record()
+            torch.cuda.synchronize()
+            gms = e0.elapsed_time(e1) / reps
+            grads[gprec] = (gms, g.cpu().numpy())
+            log("%s gradient: %.3f ms, max |dE/dR| %.3e" % (gprec, gms, np.abs(grads[gprec][1]).max()))
+            plan.close()
+            torch.cuda.empty_cache()
+        gms, gn = grads["fp64"]
         out["gradient"] = {"what": "dE_xc/dR of all %d atoms (grid held fixed), FP64 plan, one kldi_eval_grad call "
                                    "(its own rho, functional and the gradient products)" % p.n_atoms,
                            "ms": round(gms, 3), "ratio_to_fp64_energy_eval": round(gms / res["fp64"]["ms"], 3)
-                           if "fp64" in res else None, "max_abs": float(np.abs(gn).max())}
-        plan.close()
-        torch.cuda.empty_cache()
+                           if "fp64" in res else None, "max_abs": float(np.abs(gn).max()),
+                           "fp32_plan": {"ms": round(grads["fp32"][0], 3),
+                                         "max_abs_diff_vs_fp64": float(np.abs(grads["fp32"][1] - gn).max())}}
     if args.config == 1 and not args.no_dense:
         plan = Plan.from_problem(p, prec=forms[0], t_b=0.0, t_d=0.0, shell_order=so, grid_block=args.grid_block)
         info = plan.info()

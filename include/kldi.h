@@ -406,8 +406,10 @@ kldi_status kldi_eval_timing(kldi_plan *plan, double *stage_ms, int32_t *n_evals
  *   D_dev     as for kldi_eval (device, n_ao x n_ao, caller order)
  *   grad_dev  [n_atoms * 3] device, caller atom order, (x, y, z) per atom, Eh/bohr
  *   exc_dev   1 double on the device, or NULL: E_xc of the same evaluation
- * Single-molecule plans with KLDI_PREC_FP64, 128-point blocks and the analytic functional (else
- * KLDI_E_UNSUPPORTED).
+ * Single-molecule plans with KLDI_PREC_FP64 or KLDI_PREC_FP32, 128-point blocks and the analytic
+ * functional (else KLDI_E_UNSUPPORTED).  FP32 plans run the X product and the gradient products on FP32
+ * MFMA with FP64 running sums (the products' operands rounded to FP32, 32 points summed in FP32) and
+ * contract with D in FP64.
  * Allocates its workspaces on the plan on first use (KLDI_E_OOM if they do not fit); only enqueues
  * work on `stream`. */
 kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_dev, double *exc_dev, void *stream);

@@ -70,7 +70,7 @@ def exc_gradient(atom_xyz, basis, pts, weights, D, xc, rho_cut=1e-14, chunk=2048
 
 
 def exc_gradient_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1e-10, t_d=None, d_ao=32, G=128,
-                         rho_cut=1e-14, shell_order=None, return_count=False, t_grad=None):
+                         rho_cut=1e-14, shell_order=None, return_count=False, t_grad=None, magnitude=False):
     """The gradient of the block-filtered evaluation: rho, grad rho and the functional exactly as
     oracle.blocked.eval_blocked computes them at thresholds (t_b, t_d; t_d = t_b when not given), then
         dE/dR_Aa = -2 sum_{mu on A} sum_nu D_{mu nu} K^a_{mu nu},
@@ -81,7 +81,9 @@ def exc_gradient_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1
         a_pq * max|A_pr| * max|B_qr| >= t_d,
     the analogue of eq. block_pair_filter for a three-factor term (t_grad, the products' threshold, is t_d
     unless given: the library uses t_d).  return_count: also the number of executed triples over all axes
-    and products."""
+    and products.  magnitude: instead of the gradient, the same sums taken over absolute values,
+        2 sum_{mu on A} sum_nu |D_{mu nu}| sum over executed (p, q, r) of (|A| |B|^T)_{mu nu},
+    the scale against which the rounding of the products' operands and sums is bounded."""
     from . import blocked as _blocked
     if t_d is None:
         t_d = t_b
@@ -131,12 +133,15 @@ def exc_gradient_blocked(atom_xyz, basis, pts, weights, point_atom, D, xc, t_b=1
                         continue
                     for ir, (r0, r1) in enumerate(B):
                         if S_phi[ip, ir] and S_phi[iq, ir] and a[ip, iq] * mA[ip, ir] * mB[iq, ir] >= t_grad:
-                            K[p0:p1, q0:q1] += Aop[p0:p1, r0:r1] @ Bop[q0:q1, r0:r1].T
+                            if magnitude:
+                                K[p0:p1, q0:q1] += np.abs(Aop[p0:p1, r0:r1]) @ np.abs(Bop[q0:q1, r0:r1]).T
+                            else:
+                                K[p0:p1, q0:q1] += Aop[p0:p1, r0:r1] @ Bop[q0:q1, r0:r1].T
                             count += 1
-        g_ao[ax] = np.sum(Dp * K, axis=1)
+        g_ao[ax] = np.sum((np.abs(Dp) if magnitude else Dp) * K, axis=1)
     ncart = [(int(l) + 1) * (int(l) + 2) // 2 for l in basis.shell_l]
     atom_of_ao = np.repeat(np.asarray(basis.shell_atom, np.int64), ncart)[ao_perm]
     out = np.zeros((atom_xyz.shape[0], 3))
     for ax in range(3):
-        np.add.at(out[:, ax], atom_of_ao, -2.0 * g_ao[ax])
+        np.add.at(out[:, ax], atom_of_ao, (2.0 if magnitude else -2.0) * g_ao[ax])
     return (out, count) if return_count else out

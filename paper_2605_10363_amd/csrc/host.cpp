@@ -1263,7 +1263,8 @@ kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_de
   return kldi::guarded([&] {
     Plan &P = plan->impl;
     if (P.n_mol != 1) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient is for single-molecule plans");
-    if (P.opts.prec != KLDI_PREC_FP64) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient runs on FP64 plans");
+    if (P.opts.prec != KLDI_PREC_FP64 && P.opts.prec != KLDI_PREC_FP32)
+      kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient runs on FP64 and FP32 plans");
     if (P.has_mlp) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient needs the analytic functional");
     if (kldi::is_mgga_xc(P.opts.xc)) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient covers LDA and GGA functionals");
     if (P.opts.grid_block != kldi::kG) kldi::fail(KLDI_E_UNSUPPORTED, "the nuclear gradient runs on 128-point blocks");
@@ -1275,6 +1276,8 @@ kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_de
       P.grad_ws.gitem = kldi::dev_alloc<double>(P, std::max<size_t>(P.items_h.size(), 1) * 6 * 128, true);
       P.grad_ws.gao = kldi::dev_alloc<double>(P, size_t(3) * P.mols_h[0].nc * 128, true);
     }
+    if (P.opts.prec != KLDI_PREC_FP64 && !P.grad_ws.gD)
+      P.grad_ws.gD = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.n_dt, 1)) * 1024, true);
     const hipStream_t s = static_cast<hipStream_t>(stream);
     kldi::IoDev io{D_dev, nullptr, nullptr, exc_dev ? exc_dev : P.ev.escratch, nullptr};
     kldi::check_hip(kldi::launch_begin(P, io, s), "begin launch");

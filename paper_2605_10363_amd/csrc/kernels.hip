@@ -25,6 +25,7 @@
 // The two GEMM kernels run one workgroup per work item, in item order or in per-XCD queue order
 // (kldi_schedule).
 #include <algorithm>
+#include <type_traits>
 
 #include <hip/hip_bf16.h>
 
@@ -1096,6 +1097,7 @@ struct VArgs {
   unsigned long long *counters;
   QArgs q;
   int accumulate;          // FP64 operands: add to the item's partial when an earlier launch wrote one
+  int keep_diag;           // FP32 operands: also the pairs (a, a) of diagonal chunk pairs (no k_vdiag beside it)
 };
 
 
@@ -1113,7 +1115,7 @@ constexpr int NTV4 = 256;   // threads per FP32 Vxc workgroup: 4 waves, wave a o
 // workload).  MFMA step kk takes point 8 (l / 16) + kk of the sub-step, so a lane reads the 8 values of
 // its row of a slab with two 16-byte loads.  The FP32 accumulators of a pair are added to the FP64 sums
 // after each sub-step (32 points).  The diagonal pairs (a, a) of a diagonal chunk pair are k_vdiag's
-// (FP64).
+// (FP64) unless keep_diag is set (the nuclear gradient's products, which are not symmetric).
 __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
   typedef Mma<float> M;
   constexpr int kSP = 32, kNS = kG / kSP, kSlab = kD * kSP, kSlot = 8 * kSlab;
@@ -1130,7 +1132,7 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
   const int m16 = l & 15, g = l >> 4;
   const float *Pf = static_cast<const float *>(A.phi) - size_t(A.ret0) * (kD * kG);   // by retained tile
   const float *Zf = static_cast<const float *>(A.zws) - size_t(A.ret0) * (kD * kG);
-  const bool diag = it.pc == it.qc;
+  const bool diag = it.pc == it.qc && !A.keep_diag;   // its pairs (a, a) are k_vdiag's
 
   f4 acc[2][8];
   double dacc[2][8][4];
@@ -1539,9 +1541,10 @@ __global__ __launch_bounds__(NT) void k_esum(const MolDev *mol, const double *__
 
 // One workgroup per retained tile (p, r) of the chunk: which = 0: d_a Phi into Aout (and W into Wout
 // when not NULL); which = 1: Q^a into Aout.
+template <class T>
 __global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev st, int64_t ret0,
                                              const double *__restrict__ coef, int ax, int which,
-                                             double *__restrict__ Aout, double *__restrict__ Wout,
+                                             T *__restrict__ Aout, T *__restrict__ Wout,
                                              double *__restrict__ Amax, double *__restrict__ Wmax) {
   const int64_t k = ret0 + blockIdx.x;
   const int j = threadIdx.x;
@@ -1555,16 +1558,16 @@ __global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev s
   const int h0 = ax == 0 ? 0 : (ax == 1 ? 1 : 2), h1 = ax == 0 ? 1 : (ax == 1 ? 3 : 4), h2 = ax == 0 ? 2 : (ax == 1 ? 4 : 5);
   double am = 0.0, wm = 0.0;
   for (int a = B.tile_nv[p]; a < kD; ++a) {   // padding rows
-    Aout[o + a * kG] = 0.0;
-    if (Wout) Wout[o + a * kG] = 0.0;
+    Aout[o + a * kG] = T(0);
+    if (Wout) Wout[o + a * kG] = T(0);
   }
   for_tile_aos_hess(B, p, x, y, z, [&](int a, double v, const double *gr, const double *h) {
     const double av = which == 0 ? gr[ax] : c1 * h[h0] + c2 * h[h1] + c3 * h[h2];
-    Aout[o + a * kG] = av;
+    Aout[o + a * kG] = T(av);
     am = fmax(am, fabs(av));
     if (Wout) {
       const double wv = c0 * v + c1 * gr[0] + c2 * gr[1] + c3 * gr[2];
-      Wout[o + a * kG] = wv;
+      Wout[o + a * kG] = T(wv);
       wm = fmax(wm, fabs(wv));
     }
   });
@@ -1667,7 +1670,7 @@ void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
         ta.t_d = 0.0;
         ta.counters = E.counters + 4;
         for (int a = 0; a < 3; ++a) {
-          k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr, nullptr,
+          k_gterm<double><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr, nullptr,
                                       nullptr);
           ta.part = E.tpart[a];
           k_xgemm_f64<true><<<gx, NTX4, 0, s>>>(ta);
@@ -1721,6 +1724,7 @@ VArgs v_args(const Plan &P, size_t ci, const void *A, const void *B) {
   va.counters = E.counters;
   va.q = QArgs{P.vq.order, P.vq.qoff + 9 * ci};
   va.accumulate = 0;
+  va.keep_diag = 0;
   return va;
 }
 
@@ -1811,7 +1815,7 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
           tv.accumulate = 1;
           tv.counters = E.counters + 4;
           for (int a = 0; a < 3; ++a) {
-            k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr, nullptr,
+            k_gterm<double><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr, nullptr,
                                       nullptr);
             k_tscale<<<nret, kG, 0, s>>>(P.st, C.ret0, E.ctau, E.tdphi, E.tB);
             k_vgemm_f64<<<gv, NTV4, 0, s>>>(tv);
@@ -1987,39 +1991,51 @@ __global__ __launch_bounds__(NT) void k_gatom(const int *__restrict__ ao_atom, i
   grad[t] = -2.0 * s;
 }
 
+// The nuclear gradient on an FP64 plan (T = double: FP64 operands) or an FP32 plan (T = float: the X
+// product and the gradient products on FP32 MFMA with FP64 running sums, including the products' diagonal
+// tile pairs; the contraction with D in FP64).
+template <class T>
 hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
+  constexpr bool kF64 = std::is_same<T, double>::value;
   const EvalDev &E = P.ev;
   const MolDev &mo = P.mols_h[0];
   auto none = [](int) {};
-  k_dprep<double><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, static_cast<double *>(E.Dt), E.amax,
-                                        E.counters);
-  const double *Dt = static_cast<const double *>(E.Dt);
-  double *A = P.grad_ws.gA;
+  k_dprep<T><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, static_cast<T *>(E.Dt), E.amax,
+                                   E.counters);
+  double *Dt = kF64 ? static_cast<double *>(E.Dt) : P.grad_ws.gD;
+  if (!kF64) k_dprep<double><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, Dt, E.amax, E.counters);
+  T *A = reinterpret_cast<T *>(P.grad_ws.gA);
+  T *Z = static_cast<T *>(E.zws);
   for (size_t ci = 0; ci < P.chunks_h.size(); ++ci) {
     const GridChunk &C = P.chunks_h[ci];
     const int64_t nret = C.ret1 - C.ret0, nblk = C.blk1 - C.blk0, nvit = C.vit1 - C.vit0;
-    x_stage<double, 0>(P, ci, s, none);
+    x_stage<T, 0>(P, ci, s, none);
     if (nret == 0 || nvit == 0) continue;
     const int64_t gv = 8 * P.vq.maxlen_h[ci];
     const double *Am = P.grad_ws.gAmax, *Wm = P.grad_ws.gWmax, *Pm = P.st.bphi + C.ret0;   // tile maxima
     auto product = [&](const void *opA, const void *opB, const double *mA, const double *mB, int skip_diag,
                        int mode, int slot) {
       k_gmask<<<nblk, NT, 0, s>>>(m_args(P, ci), E.amax, skip_diag, mA, mB, C.ret0);
-      k_vgemm_f64<<<gv, NTV4, 0, s>>>(v_args(P, ci, opA, opB));
+      VArgs va = v_args(P, ci, opA, opB);
+      if (kF64) {
+        k_vgemm_f64<<<gv, NTV4, 0, s>>>(va);
+      } else {
+        va.keep_diag = 1;
+        k_vgemm_f32<<<gv, NTV4, 0, s>>>(va);
+      }
       k_gcontract<<<nvit, kG, 0, s>>>(P.items, C.vit0, P.st.mol, P.pair_info, E.vflag, E.vpart, Dt, mode, slot,
                                       P.grad_ws.gitem);
     };
     for (int ax = 0; ax < 3; ++ax) {
-      k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 0, A,
-                                  ax == 0 ? static_cast<double *>(E.zws) : nullptr, P.grad_ws.gAmax,
-                                  P.grad_ws.gWmax);
-      product(A, E.zws, Am, Wm, 0, 0, 2 * ax);              // (d_a Phi) W^T
+      k_gterm<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 0, A, ax == 0 ? Z : nullptr,
+                                     P.grad_ws.gAmax, P.grad_ws.gWmax);
+      product(A, Z, Am, Wm, 0, 0, 2 * ax);                  // (d_a Phi) W^T
       if (P.gga) {
-        k_gterm<<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 1, A, nullptr, P.grad_ws.gAmax,
-                                    nullptr);
+        k_gterm<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 1, A, nullptr, P.grad_ws.gAmax,
+                                       nullptr);
         product(A, E.phi, Am, Pm, 0, 0, 2 * ax + 1);        // Q^a Phi^T
       } else {
-        product(E.zws, A, Wm, Am, 1, 1, 2 * ax + 1);        // W (d_a Phi)^T of the pairs pc < qc
+        product(Z, A, Wm, Am, 1, 1, 2 * ax + 1);            // W (d_a Phi)^T of the pairs pc < qc
       }
     }
   }
@@ -2046,7 +2062,9 @@ hipError_t launch_begin(const Plan &P, const IoDev &io, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_grad(const Plan &P, double *grad, hipStream_t s) { return grad_body(P, grad, s); }
+hipError_t launch_grad(const Plan &P, double *grad, hipStream_t s) {
+  return P.opts.prec == KLDI_PREC_FP64 ? grad_body<double>(P, grad, s) : grad_body<float>(P, grad, s);
+}
 
 hipError_t launch_body(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev) {
   switch (P.opts.prec) {

@@ -1,6 +1,12 @@
-"""GPU: the nuclear gradient of E_xc with the grid held fixed (kldi_eval_grad, FP64 plans) against the
-oracle (oracle.grad): the block-filtered gradient at the same thresholds element by element, the dense
-gradient without screening, and at full size central differences of E_xc in atom positions."""
+"""GPU: the nuclear gradient of E_xc with the grid held fixed (kldi_eval_grad, FP64 and FP32 plans) against
+the oracle (oracle.grad): the block-filtered gradient at the same thresholds element by element, the dense
+gradient without screening, and at full size central differences of E_xc in atom positions.
+
+FP32 plans round the products' operands to FP32 (relative 2^-24 each) and sum 32 points of a product in
+FP32 (at most 32 roundings of 2^-24 of the sum of the terms' magnitudes) before the FP64 running sums, so
+a gradient component moves by at most 34 * 2^-24 times the same sums over absolute values
+(oracle.grad.exc_gradient_blocked(..., magnitude=True)); the FP32 X product moves rho, grad rho and with
+them the products' coefficients by a bound of the same form.  The tests allow 64 * 2^-24 of it."""
 import numpy as np
 import pytest
 
@@ -19,8 +25,12 @@ def Plan():
     return Plan
 
 
-def _grad(Plan, p, xc, with_count=False, **kw):
-    plan = Plan.from_problem(p, xc=xc, prec="fp64", **kw)
+U32 = 2.0 ** -24
+FP32_BOUND = 64 * U32
+
+
+def _grad(Plan, p, xc, with_count=False, prec="fp64", **kw):
+    plan = Plan.from_problem(p, xc=xc, prec=prec, **kw)
     D = torch.from_numpy(p.D).cuda()
     exc = torch.empty(1, dtype=torch.float64, device="cuda")
     g = plan.grad(D, exc=exc).cpu().numpy()
@@ -85,10 +95,42 @@ def test_cfg0_gradient_matches_blocked_oracle(Plan, cfg0, xc):
     assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+@pytest.mark.parametrize("shape", [(2, 10, 26, 2, 41), (5, 13, 38, 5, 43)])
+def test_fp32_gradient_within_rounding_bound_of_blocked_oracle(Plan, xc, shape):
+    n_atoms, n_rad, n_ang, n_occ, seed = shape
+    p = synth.tiny_problem(n_atoms=n_atoms, n_rad=n_rad, n_ang=n_ang, n_occ=n_occ, xc=xc, seed=seed, box_A=4.0)
+    print("case: tiny FP32 gradient %s xc=%s" % (p.name, xc), flush=True)
+    args = (p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc)
+    ref, n_ref = og.exc_gradient_blocked(*args, t_b=1e-10, return_count=True)
+    mag = og.exc_gradient_blocked(*args, t_b=1e-10, magnitude=True)
+    g, n = _grad(Plan, p, xc, with_count=True, prec="fp32")
+    err = np.abs(g - ref)
+    print("  max |dg| %.2e, max |dg| / magnitude %.2e (bound %.2e), %d product triples"
+          % (err.max(), (err / np.maximum(mag, 1e-300)).max(), FP32_BOUND, n), flush=True)
+    assert np.all(err <= FP32_BOUND * mag + 1e-14)
+    assert n == n_ref
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_cfg0_fp32_gradient_within_rounding_bound(Plan, cfg0, xc):
+    p = cfg0
+    print("case: cfg0 FP32 gradient xc=%s" % xc, flush=True)
+    args = (p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc)
+    ref, n_ref = og.exc_gradient_blocked(*args, t_b=1e-10, return_count=True)
+    mag = og.exc_gradient_blocked(*args, t_b=1e-10, magnitude=True)
+    g, n = _grad(Plan, p, xc, with_count=True, prec="fp32")
+    err = np.abs(g - ref)
+    print("  max |dg| %.2e of max |g| %.2e, max |dg| / magnitude %.2e" % (err.max(), np.abs(ref).max(),
+          (err / np.maximum(mag, 1e-300)).max()), flush=True)
+    assert np.all(err <= FP32_BOUND * mag + 1e-14)
+    assert n == n_ref
+
+
 def test_gradient_refuses_unsupported_plans(Plan):
     p = synth.tiny_problem(n_atoms=2, n_rad=10, n_ang=26, n_occ=2, seed=41)
     from paper_2605_10363_amd._lib import KldiError
-    plan = Plan.from_problem(p, prec="fp32")
+    plan = Plan.from_problem(p, prec="bf16x6")
     with pytest.raises(KldiError) as e:
         plan.grad(torch.from_numpy(p.D).cuda())
     assert e.value.status == -4
@@ -97,15 +139,20 @@ def test_gradient_refuses_unsupported_plans(Plan):
 
 @pytest.mark.timeout(600)
 def test_chain_gradient_matches_energy_differences(Plan):
-    """200-atom chain (2000 AOs, 4.53M points, PBE): the FP64 gradient of three atom coordinates against
-    central differences of E_xc (atoms moved with their basis functions, grid fixed) at thresholds
-    1e-14, where the screening sets hardly change with the displacement."""
+    """200-atom chain (2000 AOs, 4.53M points, PBE): the FP64 and FP32 gradients of three atom coordinates
+    against central differences of the FP64 E_xc (atoms moved with their basis functions, grid fixed) at
+    thresholds 1e-14, where the screening sets hardly change with the displacement."""
     p = synth.make_problem(1)
     print("case: chain gradient vs energy differences", flush=True)
     plan = Plan.from_problem(p, prec="fp64", t_b=1e-14, t_d=1e-14)
     D = torch.from_numpy(p.D).cuda()
     g = plan.grad(D).cpu().numpy()
     plan.close()
+    plan = Plan.from_problem(p, prec="fp32", t_b=1e-14, t_d=1e-14)
+    g32 = plan.grad(D).cpu().numpy()
+    plan.close()
+    print("  FP32 against FP64 gradient: max |dg| %.2e of max |g| %.2e" % (np.abs(g32 - g).max(), np.abs(g).max()),
+          flush=True)
     h = 1e-4
     for A, a in ((0, 0), (57, 1), (150, 2)):
         Es = []
@@ -117,5 +164,7 @@ def test_chain_gradient_matches_energy_differences(Plan):
             Es.append(float(pl.eval(D, vxc=False)[1].item()))
             pl.close()
         fd = (Es[0] - Es[1]) / (2 * h)
-        print("  atom %d axis %d: gradient %.10f, central difference %.10f" % (A, a, g[A, a], fd), flush=True)
+        print("  atom %d axis %d: gradient %.10f (FP32 plan %.10f), central difference %.10f"
+              % (A, a, g[A, a], g32[A, a], fd), flush=True)
         assert abs(g[A, a] - fd) <= 1e-6 * max(1.0, abs(fd))
+        assert abs(g32[A, a] - fd) <= 1e-6 * max(1.0, abs(fd))

@@ -77,3 +77,37 @@ def test_gradient_pair_filter_drops_only_bounded_triples(xc):
         assert n1 <= n0
         assert np.abs(g1 - g0).max() <= bound
     assert n1 < n0        # the largest t drops triples
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_gradient_magnitude_bounds_the_gradient(xc):
+    """magnitude=True: the same sums over |D|, |A|, |B|.  Without screening it equals the dense sums over
+    all points written out here (both products of each axis, summed over the AOs of each atom); with
+    screening it bounds the gradient component by component (triangle inequality)."""
+    p = synth.tiny_problem(n_atoms=4, n_rad=10, n_ang=26, n_occ=3, xc=xc, seed=12, box_A=4.0)
+    args = (p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc)
+    m0 = og.exc_gradient_blocked(*args, t_b=0.0, magnitude=True)
+    phi, dphi, hphi = ob.eval_ao_hess(p.atom_xyz, p.basis, p.grid.xyz)
+    X = p.D @ phi
+    rho = np.einsum("mi,mi->i", phi, X)
+    gga = xc == "pbe"
+    grad = 2.0 * np.einsum("ami,mi->ai", dphi, X) if gga else None
+    sigma = np.einsum("ai,ai->i", grad, grad) if gga else None
+    c0, cb = og._coefs(xc, rho, grad, sigma, p.grid.weight, 1e-14)
+    W = c0[None, :] * phi + (np.einsum("bi,bmi->mi", cb, dphi) if gga else 0.0)
+    ncart = [(int(l) + 1) * (int(l) + 2) // 2 for l in p.basis.shell_l]
+    atom_of_ao = np.repeat(np.asarray(p.basis.shell_atom, np.int64), ncart)
+    ref = np.zeros_like(m0)
+    for ax in range(3):
+        K = np.abs(dphi[ax]) @ np.abs(W).T
+        if gga:
+            K += np.abs(np.einsum("bi,bmi->mi", cb, hphi[ax])) @ np.abs(phi).T
+        row = np.sum(np.abs(p.D) * K, axis=1)
+        for mu, at in enumerate(atom_of_ao):
+            ref[at, ax] += 2.0 * row[mu]
+    assert np.all(m0 >= 0)
+    assert np.abs(m0 - ref).max() <= 1e-12 * ref.max()
+    g = og.exc_gradient_blocked(*args, t_b=1e-10)
+    m = og.exc_gradient_blocked(*args, t_b=1e-10, magnitude=True)
+    print(xc, "max |g| %.3e, max magnitude %.3e" % (np.abs(g).max(), m.max()))
+    assert np.all(np.abs(g) <= m * (1 + 1e-12))
