@@ -1276,6 +1276,10 @@ kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_de
       P.grad_ws.gitem = kldi::dev_alloc<double>(P, std::max<size_t>(P.items_h.size(), 1) * 6 * 128, true);
       P.grad_ws.gao = kldi::dev_alloc<double>(P, size_t(3) * P.mols_h[0].nc * 128, true);
     }
+    if (P.gga && !P.grad_ws.gQ) {
+      P.grad_ws.gQ = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.max_ret, 1)) * 4096, true);
+      P.grad_ws.gQmax = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.max_ret, 1)), true);
+    }
     if (P.opts.prec != KLDI_PREC_FP64 && !P.grad_ws.gD)
       P.grad_ws.gD = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.n_dt, 1)) * 1024, true);
     const hipStream_t s = static_cast<hipStream_t>(stream);

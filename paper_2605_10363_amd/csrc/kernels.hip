@@ -1539,13 +1539,16 @@ __global__ __launch_bounds__(NT) void k_esum(const MolDev *mol, const double *__
   if (threadIdx.x == 0) io->exc[blockIdx.x] = s[0];
 }
 
-// One workgroup per retained tile (p, r) of the chunk: which = 0: d_a Phi into Aout (and W into Wout
-// when not NULL); which = 1: Q^a into Aout.
+// One workgroup per retained tile (p, r) of the chunk, from one evaluation of the tile's values, gradients
+// and second derivatives: d_a Phi into Aout, Q^a = sum_b c_b d_a d_b Phi into Qout and W = c0 Phi + sum_b
+// c_b d_b Phi into Wout (Qout and Wout when not NULL), and, when Amax is not NULL, each tile's max |.| of
+// what it wrote for the products' pair filter.
 template <class T>
 __global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev st, int64_t ret0,
-                                             const double *__restrict__ coef, int ax, int which,
-                                             T *__restrict__ Aout, T *__restrict__ Wout,
-                                             double *__restrict__ Amax, double *__restrict__ Wmax) {
+                                             const double *__restrict__ coef, int ax, T *__restrict__ Aout,
+                                             T *__restrict__ Qout, T *__restrict__ Wout,
+                                             double *__restrict__ Amax, double *__restrict__ Qmax,
+                                             double *__restrict__ Wmax) {
   const int64_t k = ret0 + blockIdx.x;
   const int j = threadIdx.x;
   const int p = st.ret_p[k];
@@ -1556,33 +1559,42 @@ __global__ __launch_bounds__(kG) void k_gterm(BasisDev B, GridDev g, StructDev s
   const size_t o = size_t(blockIdx.x) * (kD * kG) + j;
   // second-derivative slots (xx xy xz yy yz zz) of row ax
   const int h0 = ax == 0 ? 0 : (ax == 1 ? 1 : 2), h1 = ax == 0 ? 1 : (ax == 1 ? 3 : 4), h2 = ax == 0 ? 2 : (ax == 1 ? 4 : 5);
-  double am = 0.0, wm = 0.0;
+  double am = 0.0, qm = 0.0, wm = 0.0;
   for (int a = B.tile_nv[p]; a < kD; ++a) {   // padding rows
     Aout[o + a * kG] = T(0);
+    if (Qout) Qout[o + a * kG] = T(0);
     if (Wout) Wout[o + a * kG] = T(0);
   }
   for_tile_aos_hess(B, p, x, y, z, [&](int a, double v, const double *gr, const double *h) {
-    const double av = which == 0 ? gr[ax] : c1 * h[h0] + c2 * h[h1] + c3 * h[h2];
+    const double av = gr[ax];
     Aout[o + a * kG] = T(av);
     am = fmax(am, fabs(av));
+    if (Qout) {
+      const double qv = c1 * h[h0] + c2 * h[h1] + c3 * h[h2];
+      Qout[o + a * kG] = T(qv);
+      qm = fmax(qm, fabs(qv));
+    }
     if (Wout) {
       const double wv = c0 * v + c1 * gr[0] + c2 * gr[1] + c3 * gr[2];
       Wout[o + a * kG] = T(wv);
       wm = fmax(wm, fabs(wv));
     }
   });
-  // the tile's max |A| (and max |W|) for the products' pair filter
-  __shared__ double s_m[2][2];
+  // the tile's max |A|, |Q|, |W| for the products' pair filter
+  __shared__ double s_m[2][3];
   am = wave_max(am);
+  qm = wave_max(qm);
   wm = wave_max(wm);
   if ((j & 63) == 0) {
     s_m[j >> 6][0] = am;
-    s_m[j >> 6][1] = wm;
+    s_m[j >> 6][1] = qm;
+    s_m[j >> 6][2] = wm;
   }
   __syncthreads();
   if (j == 0 && Amax) {
     Amax[blockIdx.x] = fmax(s_m[0][0], s_m[1][0]);
-    if (Wout) Wmax[blockIdx.x] = fmax(s_m[0][1], s_m[1][1]);
+    if (Qout) Qmax[blockIdx.x] = fmax(s_m[0][1], s_m[1][1]);
+    if (Wout) Wmax[blockIdx.x] = fmax(s_m[0][2], s_m[1][2]);
   }
 }
 
@@ -1670,8 +1682,8 @@ void x_stage(const Plan &P, size_t ci, hipStream_t s, Mark &&mark) {
         ta.t_d = 0.0;
         ta.counters = E.counters + 4;
         for (int a = 0; a < 3; ++a) {
-          k_gterm<double><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr, nullptr,
-                                      nullptr);
+          k_gterm<double><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, E.tdphi, nullptr,
+                                              nullptr, nullptr, nullptr, nullptr);
           ta.part = E.tpart[a];
           k_xgemm_f64<true><<<gx, NTX4, 0, s>>>(ta);
         }
@@ -1815,8 +1827,8 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
           tv.accumulate = 1;
           tv.counters = E.counters + 4;
           for (int a = 0; a < 3; ++a) {
-            k_gterm<double><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, 0, E.tdphi, nullptr, nullptr,
-                                      nullptr);
+            k_gterm<double><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, E.tdphi, nullptr,
+                                                nullptr, nullptr, nullptr, nullptr);
             k_tscale<<<nret, kG, 0, s>>>(P.st, C.ret0, E.ctau, E.tdphi, E.tB);
             k_vgemm_f64<<<gv, NTV4, 0, s>>>(tv);
           }
@@ -2005,6 +2017,7 @@ hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
   double *Dt = kF64 ? static_cast<double *>(E.Dt) : P.grad_ws.gD;
   if (!kF64) k_dprep<double><<<P.n_dt, NT, 0, s>>>(P.st.mol, P.n_mol, E.io, P.ao_perm_d, Dt, E.amax, E.counters);
   T *A = reinterpret_cast<T *>(P.grad_ws.gA);
+  T *Q = reinterpret_cast<T *>(P.grad_ws.gQ);
   T *Z = static_cast<T *>(E.zws);
   for (size_t ci = 0; ci < P.chunks_h.size(); ++ci) {
     const GridChunk &C = P.chunks_h[ci];
@@ -2012,7 +2025,8 @@ hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
     x_stage<T, 0>(P, ci, s, none);
     if (nret == 0 || nvit == 0) continue;
     const int64_t gv = 8 * P.vq.maxlen_h[ci];
-    const double *Am = P.grad_ws.gAmax, *Wm = P.grad_ws.gWmax, *Pm = P.st.bphi + C.ret0;   // tile maxima
+    const double *Am = P.grad_ws.gAmax, *Qm = P.grad_ws.gQmax, *Wm = P.grad_ws.gWmax;   // tile maxima
+    const double *Pm = P.st.bphi + C.ret0;
     auto product = [&](const void *opA, const void *opB, const double *mA, const double *mB, int skip_diag,
                        int mode, int slot) {
       k_gmask<<<nblk, NT, 0, s>>>(m_args(P, ci), E.amax, skip_diag, mA, mB, C.ret0);
@@ -2027,13 +2041,11 @@ hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
                                       P.grad_ws.gitem);
     };
     for (int ax = 0; ax < 3; ++ax) {
-      k_gterm<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 0, A, ax == 0 ? Z : nullptr,
-                                     P.grad_ws.gAmax, P.grad_ws.gWmax);
+      k_gterm<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, A, P.gga ? Q : nullptr,
+                                     ax == 0 ? Z : nullptr, P.grad_ws.gAmax, P.grad_ws.gQmax, P.grad_ws.gWmax);
       product(A, Z, Am, Wm, 0, 0, 2 * ax);                  // (d_a Phi) W^T
       if (P.gga) {
-        k_gterm<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, 1, A, nullptr, P.grad_ws.gAmax,
-                                       nullptr);
-        product(A, E.phi, Am, Pm, 0, 0, 2 * ax + 1);        // Q^a Phi^T
+        product(Q, E.phi, Qm, Pm, 0, 0, 2 * ax + 1);        // Q^a Phi^T
       } else {
         product(Z, A, Wm, Am, 1, 1, 2 * ax + 1);            // W (d_a Phi)^T of the pairs pc < qc
       }

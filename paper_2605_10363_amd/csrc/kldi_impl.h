@@ -211,6 +211,8 @@ struct Plan {
     double *gA = nullptr;     // [max chunk retained tiles * 4096] operand of the gradient products
     double *gAmax = nullptr;  // [max chunk retained tiles] max |gA| of each tile
     double *gWmax = nullptr;  // [max chunk retained tiles] max |W| of each tile (W in the Z workspace)
+    double *gQ = nullptr;     // GGA: [max chunk retained tiles * 4096] Q^a, the second operand of the products
+    double *gQmax = nullptr;  // GGA: [max chunk retained tiles] max |Q^a| of each tile
     double *gD = nullptr;     // FP32 plans: D as FP64 32 x 32 tiles for the contraction of the products
     double *gitem = nullptr;  // [n_items][6][128] per-item contracted partials
     double *gao = nullptr;    // [3][nc * 128] per-AO sums
