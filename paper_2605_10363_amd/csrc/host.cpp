@@ -1275,6 +1275,7 @@ kldi_status kldi_eval_grad(kldi_plan *plan, const double *D_dev, double *grad_de
       P.grad_ws.gWmax = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.max_ret, 1)), true);
       P.grad_ws.gitem = kldi::dev_alloc<double>(P, std::max<size_t>(P.items_h.size(), 1) * 6 * 128, true);
       P.grad_ws.gao = kldi::dev_alloc<double>(P, size_t(3) * P.mols_h[0].nc * 128, true);
+      P.grad_ws.gpart = kldi::dev_alloc<double>(P, size_t(P.mols_h[0].nc) * kldi::kGSeg * 3 * 128, true);
     }
     if (P.gga && !P.grad_ws.gQ) {
       P.grad_ws.gQ = kldi::dev_alloc<double>(P, size_t(std::max<int64_t>(P.max_ret, 1)) * 4096, true);

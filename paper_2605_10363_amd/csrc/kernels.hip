@@ -1957,35 +1957,62 @@ __global__ __launch_bounds__(kG) void k_gcontract(const VItem *__restrict__ item
   gitem[(size_t(item) * 6 + slot) * 128 + i] = s;
 }
 
-// One workgroup per row chunk c of the molecule: the per-AO gradient sums of the 128 AOs of c, over the
-// items in a fixed order (pairs in index order, a pair's items in segment order).  Slots per item:
-// 2a and 2a+1 for component a; GGA: both are row sums of items with pc = c; LDA: slot 2a row sums of
-// items with pc = c, slot 2a+1 column sums of items with qc = c > pc.
-__global__ __launch_bounds__(kG) void k_greduce(const MolDev *__restrict__ mol, const int *__restrict__ pair_ptr,
-                                               const int *__restrict__ pair_items, const int *__restrict__ pair_info,
-                                               const double *__restrict__ gitem, int lda, double *__restrict__ gao,
-                                               int ld) {
+// The per-AO gradient sums of the 128 AOs of row chunk c over the items of the chunk's pairs, in a fixed
+// order: the pairs of chunk c in pair order -- (pc, c) for pc < c (LDA plans, which hold pc <= qc: its
+// columns), then (c, qc) (its rows); pair index pc nc + qc (GGA) or pc nc - pc (pc - 1) / 2 + (qc - pc)
+// (LDA) -- and a pair's items in segment order.  Slots per item: 2a and 2a+1 for component a; GGA: both
+// are row sums of items with pc = c; LDA: slot 2a row sums of items with pc = c, slot 2a+1 column sums of
+// items with qc = c > pc.  That sequence is cut into kGSeg equal parts: k_greduce_part sums part s of
+// chunk c (one workgroup per (c, s)), k_greduce the kGSeg partial sums of each AO in order.
+
+// calls f(item, column) for the items of positions [lo, hi) of chunk c's sequence; returns its length
+template <class F>
+__device__ __forceinline__ int greduce_walk(const MolDev &mo, const int *pair_ptr, int lda, int c, int lo, int hi,
+                                            F &&f) {
+  const int nc = mo.nc;
+  int pos = 0;
+  auto pair = [&](int pr, bool col) {
+    const int k0 = pair_ptr[pr], n = pair_ptr[pr + 1] - k0;
+    const int a = max(lo - pos, 0), b = min(hi - pos, n);
+    for (int k = a; k < b; ++k) f(k0 + k, col);
+    pos += n;
+  };
+  if (lda)
+    for (int pc = 0; pc < c; ++pc) pair(mo.pair0 + pc * nc - pc * (pc - 1) / 2 + (c - pc), true);
+  for (int qc = lda ? c : 0; qc < nc; ++qc) pair(mo.pair0 + (lda ? c * nc - c * (c - 1) / 2 + (qc - c) : c * nc + qc), false);
+  return pos;
+}
+
+__global__ __launch_bounds__(kG) void k_greduce_part(const MolDev *__restrict__ mol, const int *__restrict__ pair_ptr,
+                                                    const int *__restrict__ pair_items,
+                                                    const double *__restrict__ gitem, int lda,
+                                                    double *__restrict__ gpart) {
   const MolDev mo = mol[0];
-  const int c = blockIdx.x, i = threadIdx.x, nc = mo.nc;
-  // the pairs of chunk c in pair order: (pc, c) for pc < c (LDA plans, which hold pc <= qc: its columns),
-  // then (c, qc) (its rows); pair index pc nc + qc (GGA) or pc nc - pc (pc - 1) / 2 + (qc - pc) (LDA)
+  const int c = blockIdx.x / kGSeg, sg = blockIdx.x % kGSeg, i = threadIdx.x;
+  const int n = greduce_walk(mo, pair_ptr, lda, c, 0, 0, [](int, bool) {});
+  const int lo = int(int64_t(n) * sg / kGSeg), hi = int(int64_t(n) * (sg + 1) / kGSeg);
+  double s[3] = {0.0, 0.0, 0.0};
+  greduce_walk(mo, pair_ptr, lda, c, lo, hi, [&](int k, bool col) {
+    const double *gi = gitem + size_t(pair_items[k]) * 6 * 128 + i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (col) {
+        s[a] += gi[(2 * a + 1) * 128];
+      } else {
+        s[a] += gi[(2 * a) * 128];
+        if (!lda) s[a] += gi[(2 * a + 1) * 128];
+      }
+    }
+  });
+#pragma unroll
+  for (int a = 0; a < 3; ++a) gpart[(size_t(blockIdx.x) * 3 + a) * 128 + i] = s[a];
+}
+
+__global__ __launch_bounds__(kG) void k_greduce(const double *__restrict__ gpart, double *__restrict__ gao, int ld) {
+  const int c = blockIdx.x, i = threadIdx.x;
   for (int a = 0; a < 3; ++a) {
     double s = 0.0;
-    if (lda) {
-      for (int pc = 0; pc < c; ++pc) {
-        const int pr = mo.pair0 + pc * nc - pc * (pc - 1) / 2 + (c - pc);
-        for (int k = pair_ptr[pr]; k < pair_ptr[pr + 1]; ++k)
-          s += gitem[size_t(pair_items[k]) * 6 * 128 + (2 * a + 1) * 128 + i];
-      }
-    }
-    for (int qc = lda ? c : 0; qc < nc; ++qc) {
-      const int pr = mo.pair0 + (lda ? c * nc - c * (c - 1) / 2 + (qc - c) : c * nc + qc);
-      for (int k = pair_ptr[pr]; k < pair_ptr[pr + 1]; ++k) {
-        const double *gi = gitem + size_t(pair_items[k]) * 6 * 128 + i;
-        s += gi[(2 * a) * 128];
-        if (!lda) s += gi[(2 * a + 1) * 128];
-      }
-    }
+    for (int sg = 0; sg < kGSeg; ++sg) s += gpart[((size_t(c) * kGSeg + sg) * 3 + a) * 128 + i];
     gao[size_t(a) * ld + size_t(c) * 128 + i] = s;
   }
 }
@@ -2053,8 +2080,9 @@ hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
   }
   k_esum<<<P.n_mol, NT, 0, s>>>(P.st.mol, E.eblk, E.io);
   const int ld = mo.nc * 128;
-  k_greduce<<<mo.nc, kG, 0, s>>>(P.st.mol, P.pair_ptr, P.pair_items, P.pair_info, P.grad_ws.gitem, P.gga ? 0 : 1,
-                                 P.grad_ws.gao, ld);
+  k_greduce_part<<<mo.nc * kGSeg, kG, 0, s>>>(P.st.mol, P.pair_ptr, P.pair_items, P.grad_ws.gitem, P.gga ? 0 : 1,
+                                              P.grad_ws.gpart);
+  k_greduce<<<mo.nc, kG, 0, s>>>(P.grad_ws.gpart, P.grad_ws.gao, ld);
   k_gatom<<<(3 * P.n_atoms0 + NT - 1) / NT, NT, 0, s>>>(P.ao_atom, mo.n_ao, P.n_atoms0, P.grad_ws.gao, ld,
                                                        grad);
   return hipGetLastError();

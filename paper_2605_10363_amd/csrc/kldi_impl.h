@@ -13,6 +13,7 @@ namespace kldi {
 
 constexpr int kG = 128;          // points per grid block
 constexpr int kD = 32;           // AOs per tile
+constexpr int kGSeg = 64;        // parts of each row chunk's item sequence in the gradient's final reduction
 constexpr int kChunk = 4;        // AO tiles per workgroup row chunk (one per wave)
 constexpr int kMaxTilesPerBlock = 512;
 // Largest plan (in grid blocks) the queue schedule accepts.  A persistent form of that schedule
@@ -213,6 +214,7 @@ struct Plan {
     double *gWmax = nullptr;  // [max chunk retained tiles] max |W| of each tile (W in the Z workspace)
     double *gQ = nullptr;     // GGA: [max chunk retained tiles * 4096] Q^a, the second operand of the products
     double *gQmax = nullptr;  // GGA: [max chunk retained tiles] max |Q^a| of each tile
+    double *gpart = nullptr;  // [row chunks * kGSeg * 3 * 128] partial per-AO sums of the final reduction
     double *gD = nullptr;     // FP32 plans: D as FP64 32 x 32 tiles for the contraction of the products
     double *gitem = nullptr;  // [n_items][6][128] per-item contracted partials
     double *gao = nullptr;    // [3][nc * 128] per-AO sums
