@@ -1081,6 +1081,17 @@ __global__ __launch_bounds__(NT) void k_vmask(VMaskArgs A) {
   }
 }
 
+// Gradient products: each item's 128 x 128 partial (rows: AOs of row chunk pc, columns: AOs of column chunk
+// qc) times D element by element, summed along each row (mode 0: one sum per row AO) or each column (mode 1:
+// one per column AO), into slot `slot` of the item's gradient partial (zeros where nothing executed),
+// formed from the Vxc kernels' accumulators instead of a stored partial.
+struct GContract {
+  const int *pair_info;    // [3 * pairs]: the molecule of each chunk pair in entry 2
+  const double *Dt;        // D as FP64 32 x 32 tiles
+  double *gitem;           // [items * 6 * 128]
+  int mode, slot;
+};
+
 struct VArgs {
   StructDev st;
   const VItem *items;
@@ -1098,7 +1109,65 @@ struct VArgs {
   QArgs q;
   int accumulate;          // FP64 operands: add to the item's partial when an earlier launch wrote one
   int keep_diag;           // FP32 operands: also the pairs (a, a) of diagonal chunk pairs (no k_vdiag beside it)
+  GContract gc;            // contracting kernels (gradient products): where the contractions go
 };
+
+// The contraction of GContract from the accumulators of a Vxc kernel: wave w holds tile pair (a, (w - a)
+// mod 4) for a = 0..3, val(a, ti, tj, v) at row 32 a + 16 ti + row(v), column 32 b + 16 tj + (lane % 16).
+// A wave's 4 pairs cover every row (and every column) of the chunk pair once, so each wave sums its part
+// of every row (column) over the 16 lanes (4 lane groups) that hold it, and the 4 waves' parts are added in
+// wave order.
+template <class Val, class Row>
+__device__ __forceinline__ void grad_contract(const VArgs &A, const VItem &it, int64_t item, bool any, int ws,
+                                              double (*s_red)[128], Val &&val, Row &&row) {
+  const int tid = threadIdx.x, l = tid & 63, m16 = l & 15, g = l >> 4;
+  double *gout = A.gc.gitem + (size_t(item) * 6 + A.gc.slot) * 128;
+  if (!any) {
+    if (tid < 128) gout[tid] = 0.0;
+    return;
+  }
+  const MolDev mo = A.st.mol[A.gc.pair_info[3 * it.pair + 2]];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int b = (ws - a) & 3, p = 4 * it.pc + a, q = 4 * it.qc + b;
+    const bool ok = p < mo.nt && q < mo.nt;   // tiles past the molecule's AOs: D = 0
+    const double *dt = A.gc.Dt + (size_t(mo.dt0) + size_t(p) * mo.nt + q) * 1024;
+    if (A.gc.mode == 0) {
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * ti + row(v);
+          double sm = 0.0;
+          if (ok) {
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj) sm += val(a, ti, tj, v) * dt[r * 32 + 16 * tj + m16];
+          }
+          sm += __shfl_xor(sm, 1);
+          sm += __shfl_xor(sm, 2);
+          sm += __shfl_xor(sm, 4);
+          sm += __shfl_xor(sm, 8);
+          if (m16 == 0) s_red[ws][32 * a + r] = sm;
+        }
+    } else {
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        double sm = 0.0;
+        if (ok) {
+#pragma unroll
+          for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sm += val(a, ti, tj, v) * dt[(16 * ti + row(v)) * 32 + 16 * tj + m16];
+        }
+        sm += __shfl_xor(sm, 16);
+        sm += __shfl_xor(sm, 32);
+        if (g == 0) s_red[ws][32 * b + 16 * tj + m16] = sm;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < 128) gout[tid] = (s_red[0][tid] + s_red[1][tid]) + (s_red[2][tid] + s_red[3][tid]);
+}
 
 
 constexpr int NTV4 = 256;   // threads per FP32 Vxc workgroup: 4 waves, wave a owns row tile a (32 x 128)
@@ -1115,7 +1184,9 @@ constexpr int NTV4 = 256;   // threads per FP32 Vxc workgroup: 4 waves, wave a o
 // workload).  MFMA step kk takes point 8 (l / 16) + kk of the sub-step, so a lane reads the 8 values of
 // its row of a slab with two 16-byte loads.  The FP32 accumulators of a pair are added to the FP64 sums
 // after each sub-step (32 points).  The diagonal pairs (a, a) of a diagonal chunk pair are k_vdiag's
-// (FP64) unless keep_diag is set (the nuclear gradient's products, which are not symmetric).
+// (FP64) unless keep_diag is set (the nuclear gradient's products, which are not symmetric).  CONTRACT: the
+// item's partial goes into its gradient contraction (GContract) instead of vpart.
+template <bool CONTRACT>
 __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
   typedef Mma<float> M;
   constexpr int kSP = 32, kNS = kG / kSP, kSlab = kD * kSP, kSlot = 8 * kSlab;
@@ -1234,26 +1305,33 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
     }
     __syncthreads();
   }
-  if (!any) {
-    if (tid == 0 && !A.accumulate) A.vflag[item] = 0;
-    return;
+  if constexpr (CONTRACT) {
+    // the ring is free after the loop's last barrier
+    grad_contract(A, it, item, any != 0, ws, reinterpret_cast<double (*)[128]>(ring),
+                  [&](int a, int ti, int tj, int v) { return dacc[ti][2 * a + tj][v]; },
+                  [&](int v) { return M::row(v, l); });
+  } else {
+    if (!any) {
+      if (tid == 0 && !A.accumulate) A.vflag[item] = 0;
+      return;
+    }
+    double *out = A.vpart + size_t(item) * (128 * 128);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int b = (ws - a) & 3;
+      if (diag && a == b) continue;           // written by k_vdiag
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 32 * a + 16 * ti + M::row(v, l), col = 32 * b + 16 * tj + m16;
+            out[row * 128 + col] = dacc[ti][2 * a + tj][v];
+          }
+    }
+    if (tid == 0) A.vflag[item] = 1;
   }
-  double *out = A.vpart + size_t(item) * (128 * 128);
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int b = (ws - a) & 3;
-    if (diag && a == b) continue;           // written by k_vdiag
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 32 * a + 16 * ti + M::row(v, l), col = 32 * b + 16 * tj + m16;
-          out[row * 128 + col] = dacc[ti][2 * a + tj][v];
-        }
-  }
-  if (tid == 0) A.vflag[item] = 1;
   double pd = wave_sum(double(pairs));
   if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
   });
@@ -1262,7 +1340,8 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f32(VArgs A) {
 // FP64 operands: the 4-wave Vxc kernel of k_vgemm_f32 on v_mfma_f64_16x16x4f64 (same items and pair
 // ownership), with 16-point sub-steps so that a ring slot (4 Phi slabs and 4 Z slabs of 32 x 16) stays
 // 32 KB; MFMA step kk takes point 4 (l / 16) + kk of the sub-step.  With `accumulate` set, an item whose
-// partial an earlier launch wrote adds to it (the meta-GGA term).
+// partial an earlier launch wrote adds to it (the meta-GGA term).  CONTRACT as for k_vgemm_f32.
+template <bool CONTRACT>
 __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
   typedef Mma<double> M;
   typedef double d2 __attribute__((ext_vector_type(2)));
@@ -1362,26 +1441,32 @@ __global__ __launch_bounds__(NTV4, 2) void k_vgemm_f64(VArgs A) {
     }
     __syncthreads();
   }
-  if (!any) {
-    if (tid == 0 && !A.accumulate) A.vflag[item] = 0;
-    return;
+  if constexpr (CONTRACT) {
+    grad_contract(A, it, item, any != 0, ws, reinterpret_cast<double (*)[128]>(ring),
+                  [&](int a, int ti, int tj, int v) { return acc[ti][2 * a + tj][v]; },
+                  [&](int v) { return M::row(v, l); });
+  } else {
+    if (!any) {
+      if (tid == 0 && !A.accumulate) A.vflag[item] = 0;
+      return;
+    }
+    double *out = A.vpart + size_t(item) * (128 * 128);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int b = (ws - a) & 3;
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 32 * a + 16 * ti + M::row(v, l), col = 32 * b + 16 * tj + m16;
+            const double val = acc[ti][2 * a + tj][v];
+            out[row * 128 + col] = prev ? out[row * 128 + col] + val : val;
+          }
+    }
+    if (tid == 0) A.vflag[item] = 1;
   }
-  double *out = A.vpart + size_t(item) * (128 * 128);
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int b = (ws - a) & 3;
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 32 * a + 16 * ti + M::row(v, l), col = 32 * b + 16 * tj + m16;
-          const double val = acc[ti][2 * a + tj][v];
-          out[row * 128 + col] = prev ? out[row * 128 + col] + val : val;
-        }
-  }
-  if (tid == 0) A.vflag[item] = 1;
   double pd = wave_sum(double(pairs));
   if (l == 0 && pd > 0) atomicAdd(&A.counters[1], (unsigned long long)(pd + 0.5));
   });
@@ -1812,9 +1897,9 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
       }
       if (nvit > 0) {
         if constexpr (sizeof(T) == 4)
-          k_vgemm_f32<<<gv, NTV4, 0, s>>>(va);
+          k_vgemm_f32<false><<<gv, NTV4, 0, s>>>(va);
         else
-          k_vgemm_f64<<<gv, NTV4, 0, s>>>(va);
+          k_vgemm_f64<false><<<gv, NTV4, 0, s>>>(va);
       }
       if constexpr (sizeof(T) == 8 && NPC == 0) {
         if (is_mgga_xc(P.opts.xc) && nvit > 0 && nret > 0) {
@@ -1830,7 +1915,7 @@ hipError_t body_typed(const Plan &P, bool want_v, hipStream_t s, hipEvent_t *ev)
             k_gterm<double><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, a, E.tdphi, nullptr,
                                                 nullptr, nullptr, nullptr, nullptr);
             k_tscale<<<nret, kG, 0, s>>>(P.st, C.ret0, E.ctau, E.tdphi, E.tB);
-            k_vgemm_f64<<<gv, NTV4, 0, s>>>(tv);
+            k_vgemm_f64<false><<<gv, NTV4, 0, s>>>(tv);
           }
         }
       }
@@ -1914,47 +1999,6 @@ __global__ __launch_bounds__(NT) void k_gmask(VMaskArgs A, const double *__restr
     }
     out[pr] = (unsigned short)mask;
   }
-}
-
-// One workgroup (128 threads) per Vxc item of the launch: its partial P (rows: AOs of row chunk pc,
-// columns: AOs of column chunk qc) times D element by element, summed along each row (mode 0: one sum
-// per row AO) or each column (mode 1: one per column AO), into slot `slot` of the item's gradient
-// partial (zeros where the item executed nothing).
-__global__ __launch_bounds__(kG) void k_gcontract(const VItem *__restrict__ items, int64_t item0,
-                                                 const MolDev *__restrict__ mol, const int *__restrict__ pair_info,
-                                                 const int *__restrict__ vflag, const double *__restrict__ vpart,
-                                                 const double *__restrict__ Dt, int mode, int slot,
-                                                 double *__restrict__ gitem) {
-  const int64_t item = item0 + blockIdx.x;
-  const VItem it = items[item];
-  const MolDev mo = mol[pair_info[3 * it.pair + 2]];
-  const int i = threadIdx.x;
-  double s = 0.0;
-  __shared__ double s_pd[128][33];   // row sums: P .* D of 32 columns, rows padded against bank conflicts
-  if (vflag[item]) {
-    const double *Pp = vpart + size_t(item) * 16384;
-    auto d = [&](int row, int col) {   // D of AO row of chunk pc, AO col of chunk qc
-      const int p = 4 * it.pc + (row >> 5), q = 4 * it.qc + (col >> 5);
-      if (p >= mo.nt || q >= mo.nt) return 0.0;
-      return Dt[(size_t(mo.dt0) + size_t(p) * mo.nt + q) * 1024 + (row & 31) * 32 + (col & 31)];
-    };
-    if (mode == 0) {
-      // 32 columns at a time: the products are formed with coalesced reads (a row of 32 columns per 32
-      // threads), then each thread sums its row in column order
-      for (int jb = 0; jb < 128; jb += 32) {
-        for (int e = i; e < 128 * 32; e += 128) {
-          const int row = e >> 5, col = jb + (e & 31);
-          s_pd[row][e & 31] = d(row, col) * Pp[row * 128 + col];
-        }
-        __syncthreads();
-        for (int c = 0; c < 32; ++c) s += s_pd[i][c];
-        __syncthreads();
-      }
-    } else {
-      for (int j = 0; j < 128; ++j) s += d(j, i) * Pp[j * 128 + i];
-    }
-  }
-  gitem[(size_t(item) * 6 + slot) * 128 + i] = s;
 }
 
 // The per-AO gradient sums of the 128 AOs of row chunk c over the items of the chunk's pairs, in a fixed
@@ -2058,14 +2102,13 @@ hipError_t grad_body(const Plan &P, double *grad, hipStream_t s) {
                        int mode, int slot) {
       k_gmask<<<nblk, NT, 0, s>>>(m_args(P, ci), E.amax, skip_diag, mA, mB, C.ret0);
       VArgs va = v_args(P, ci, opA, opB);
+      va.gc = GContract{P.pair_info, Dt, P.grad_ws.gitem, mode, slot};
       if (kF64) {
-        k_vgemm_f64<<<gv, NTV4, 0, s>>>(va);
+        k_vgemm_f64<true><<<gv, NTV4, 0, s>>>(va);
       } else {
         va.keep_diag = 1;
-        k_vgemm_f32<<<gv, NTV4, 0, s>>>(va);
+        k_vgemm_f32<true><<<gv, NTV4, 0, s>>>(va);
       }
-      k_gcontract<<<nvit, kG, 0, s>>>(P.items, C.vit0, P.st.mol, P.pair_info, E.vflag, E.vpart, Dt, mode, slot,
-                                      P.grad_ws.gitem);
     };
     for (int ax = 0; ax < 3; ++ax) {
       k_gterm<T><<<nret, kG, 0, s>>>(P.basis, P.grid, P.st, C.ret0, E.coef, ax, A, P.gga ? Q : nullptr,

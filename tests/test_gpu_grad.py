@@ -127,6 +127,27 @@ def test_cfg0_fp32_gradient_within_rounding_bound(Plan, cfg0, xc):
     assert n == n_ref
 
 
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gradient_grid_chunks_give_identical_results(Plan, cfg0, xc, prec):
+    """The gradient of a plan that processes the grid in several chunks (small Phi/Z workspaces) equals that
+    of one chunk bit for bit: the same items run, each writes its own partial, and the reduction keeps
+    its order."""
+    p = cfg0
+    outs = []
+    for ct in (0, 40):
+        print("case: cfg0 gradient xc=%s prec=%s chunk_tiles=%d" % (xc, prec, ct), flush=True)
+        plan = Plan.from_problem(p, xc=xc, prec=prec, v_segment=16, chunk_tiles=ct)
+        n_chunks = plan.info()["n_grid_chunks"]
+        g = plan.grad(torch.from_numpy(p.D).cuda()).cpu().numpy()
+        outs.append((g, plan.check()["n_pairs_v"], n_chunks))
+        plan.close()
+    (ga, na, ca), (gb, nb, cb) = outs
+    assert ca == 1 and cb > 1
+    assert na == nb
+    assert np.array_equal(ga, gb)
+
+
 def test_gradient_refuses_unsupported_plans(Plan):
     p = synth.tiny_problem(n_atoms=2, n_rad=10, n_ang=26, n_occ=2, seed=41)
     from paper_2605_10363_amd._lib import KldiError
