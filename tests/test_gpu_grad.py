@@ -113,6 +113,26 @@ def test_fp32_gradient_within_rounding_bound_of_blocked_oracle(Plan, xc, shape):
 
 
 @pytest.mark.parametrize("xc", ["lda", "pbe"])
+def test_fp32_gradient_pair_filter_and_unscreened(Plan, xc):
+    """FP32 plans: with a pair threshold that drops product triples (t_d = 1e-6) the executed triples are the
+    oracle's, and without screening the gradient meets the dense oracle; both within the rounding bound."""
+    p = synth.tiny_problem(n_atoms=5, n_rad=14, n_ang=38, n_occ=5, xc=xc, seed=47, box_A=5.0)
+    print("case: FP32 gradient pair filter / unscreened %s xc=%s" % (p.name, xc), flush=True)
+    args = (p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, p.D, xc)
+    for t_b, t_d in ((1e-10, 1e-6), (0.0, 0.0)):
+        ref, n_ref = og.exc_gradient_blocked(*args, t_b=t_b, t_d=t_d, return_count=True)
+        mag = og.exc_gradient_blocked(*args, t_b=t_b, t_d=t_d, magnitude=True)
+        g, n = _grad(Plan, p, xc, with_count=True, prec="fp32", t_b=t_b, t_d=t_d)
+        err = np.abs(g - ref)
+        print("  t_b %.0e t_d %.0e: %d product triples, max |dg| / magnitude %.2e"
+              % (t_b, t_d, n, (err / np.maximum(mag, 1e-300)).max()), flush=True)
+        assert n == n_ref
+        assert np.all(err <= FP32_BOUND * mag + 1e-14)
+    dense = og.exc_gradient(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.D, xc)
+    assert np.abs(ref - dense).max() <= 1e-12 * np.abs(dense).max()   # t = 0: the blocked form is the dense one
+
+
+@pytest.mark.parametrize("xc", ["lda", "pbe"])
 def test_cfg0_fp32_gradient_within_rounding_bound(Plan, cfg0, xc):
     p = cfg0
     print("case: cfg0 FP32 gradient xc=%s" % xc, flush=True)
