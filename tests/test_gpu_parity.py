@@ -97,7 +97,7 @@ def test_cfg0_fp64_and_fp32(Plan, cfg0):
     assert np.abs(g["rho"] - ref["rho"]).max() <= 1e-12 * np.abs(ref["rho"]).max()
     assert (g["stats"]["n_pairs_x"], g["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
     assert g["stats"]["n_pairs_v_diag"] == 0
-    # spec accuracy of the FP32 form against the unscreened FP64 oracle
+    # accuracy targets of the FP32 form (1e-6 Eh, 1e-7 in Vxc) against the unscreened FP64 oracle
     f = run(Plan, p, "lda", "fp32")
     # the FP32 plan runs the same triples, its diagonal ones (p, p, r) on the FP64 diagonal kernel
     assert (f["stats"]["n_pairs_x"], f["stats"]["n_pairs_v"]) == (ref["nP_X"], ref["nP_M"])
