@@ -168,6 +168,25 @@ def test_gradient_grid_chunks_give_identical_results(Plan, cfg0, xc, prec):
     assert np.array_equal(ga, gb)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gradient_degenerate_inputs_give_exact_zeros(Plan, prec):
+    """D = 0 (no D block retained, rho = 0 below the density floor: every coefficient vanishes) and a
+    threshold that retains no basis tile both give a gradient of exact zeros with no product executed, as
+    the oracle's definition does."""
+    p = synth.tiny_problem(n_atoms=3, n_rad=10, n_ang=26, n_occ=3, xc="pbe", seed=45, box_A=4.0)
+    for D, t_b in ((np.zeros_like(p.D), 1e-10), (p.D, 1e30)):
+        print("case: degenerate gradient prec=%s t_b=%.0e |D|=%.1f" % (prec, t_b, np.abs(D).max()), flush=True)
+        plan = Plan.from_problem(p, xc="pbe", prec=prec, t_b=t_b, t_d=t_b)
+        g = plan.grad(torch.from_numpy(np.ascontiguousarray(D)).cuda()).cpu().numpy()
+        n = plan.check()["n_pairs_v"]
+        plan.close()
+        ref = og.exc_gradient_blocked(p.atom_xyz, p.basis, p.grid.xyz, p.grid.weight, p.grid.point_atom, D, "pbe",
+                                      t_b=t_b, t_d=t_b)
+        assert np.all(ref == 0.0)
+        assert np.all(g == 0.0)
+        assert n == 0
+
+
 def test_gradient_refuses_unsupported_plans(Plan):
     p = synth.tiny_problem(n_atoms=2, n_rad=10, n_ang=26, n_occ=2, seed=41)
     from paper_2605_10363_amd._lib import KldiError
