@@ -149,16 +149,22 @@ def blas_vendor():
         return "unknown"
 
 
-def sweep(p, D, steps, warmup, torch, Plan, gd, so=None):
-    """Thresholds t_b = t_d = t on the mixed path: retained fraction, executed pairs, ms/eval, and the
-    errors of E_xc and of sampled Vxc entries against the unscreened FP64 oracle (gd) and against the
-    FP64 GPU path at the same thresholds."""
+SWEEP_T = [(t, t) for t in (1e-8, 1e-9, 1e-10, 1e-11, 1e-12, 1e-14, 0.0)]
+# the pair threshold alone (Sec. IV-A's t_d sensitivity) at the paper's block threshold t_b = 1e-12
+SWEEP_TD = [(1e-12, t) for t in (1e-4, 1e-6, 1e-8, 1e-10, 1e-12, 0.0)]
+
+
+def sweep(p, D, steps, warmup, torch, Plan, gd, so=None, pairs=SWEEP_T, precs=("fp32", "fp64")):
+    """Thresholds (t_b, t_d) on the mixed path (and the FP64 path): retained fraction, executed pairs,
+    ms/eval, and the errors of E_xc and of sampled Vxc entries against the unscreened FP64 oracle (gd) and
+    against the FP64 GPU path at the same thresholds."""
     ij = np.array(gd["v_ij"])
     rows = []
-    for t in (1e-8, 1e-9, 1e-10, 1e-11, 1e-12, 1e-14, 0.0):
-        r = {"t": t}
-        for prec in ("fp32", "fp64"):
-            plan = Plan.from_problem(p, prec=prec, t_b=t, t_d=t, shell_order=so)
+    for t_b, t_d in pairs:
+        t = t_d
+        r = {"t": t_d, "t_b": t_b, "t_d": t_d}
+        for prec in precs:
+            plan = Plan.from_problem(p, prec=prec, t_b=t_b, t_d=t_d, shell_order=so)
             info = plan.info()
             ms, stage, st, E, V, rho = time_path(plan, D, steps, warmup, torch)
             dv = max(np.abs(V[ij[:, 0], ij[:, 1]] - np.array(gd["v"])).max(),
@@ -171,11 +177,12 @@ def sweep(p, D, steps, warmup, torch, Plan, gd, so=None):
             plan.close()
             del rho
             torch.cuda.empty_cache()
-            log("sweep t=%g %s: %.2f ms, retained %.4f, dE vs dense %.2e, dV %.2e" % (
-                t, prec, ms, info["retained_fraction"], abs(E - gd["E"]), dv))
-        r["fp32"]["dE_vs_fp64"] = abs(r["fp32"]["E"] - r["fp64"]["E"])
-        r["fp32"]["dV_vs_fp64"] = float(np.abs(r["fp32"]["V"] - r["fp64"]["V"]).max())
-        for prec in ("fp32", "fp64"):
+            log("sweep t_b=%g t_d=%g %s: %.2f ms, retained %.4f, pairs x %d v %d, dE vs dense %.2e, dV %.2e" % (
+                t_b, t, prec, ms, info["retained_fraction"], st["n_pairs_x"], st["n_pairs_v"], abs(E - gd["E"]), dv))
+        if "fp64" in r and "fp32" in r:
+            r["fp32"]["dE_vs_fp64"] = abs(r["fp32"]["E"] - r["fp64"]["E"])
+            r["fp32"]["dV_vs_fp64"] = float(np.abs(r["fp32"]["V"] - r["fp64"]["V"]).max())
+        for prec in precs:
             del r[prec]["V"]
         rows.append(r)
     return rows
@@ -482,7 +489,9 @@ def main():
     if args.sweep:
         gd = json.load(open(GOLDEN))
         rows = sweep(p, D, args.steps, args.warmup, torch, Plan, gd, so)
-        print(json.dumps({"workload": workload_name(args.config, args.grid_block), "sweep": rows}), flush=True)
+        rows_td = sweep(p, D, args.steps, args.warmup, torch, Plan, gd, so, pairs=SWEEP_TD, precs=("fp32",))
+        print(json.dumps({"workload": workload_name(args.config, args.grid_block), "sweep": rows,
+                          "sweep_td_at_tb_1e-12": rows_td}), flush=True)
         return
     res = {}
     forms = [f for f in args.precs.split(",") if f]
