@@ -428,6 +428,10 @@ def main():
                     help="training epochs of the learned form (--config 4), in three equal phases at learning rates "
                          "2e-3, 5e-4 and 1.25e-4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense", action="store_true",
+                    help="also time the unscreened comparator at workloads other than 0 and 1 (size sweep)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="workload 4: time the analytic functional on the main path instead of the learned form")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="threshold sweep t_b = t_d on workload 1 (retained fraction, time, errors) instead of the bench")
@@ -462,7 +466,7 @@ def main():
     if args.config == 3:
         bench_batch(args, torch)
         return
-    if args.config == 4:
+    if args.config == 4 and not args.no_learned:
         bench_learned(args, torch)
         return
 
@@ -598,7 +602,7 @@ def main():
                            if "fp64" in res else None, "max_abs": float(np.abs(gn).max()),
                            "fp32_plan": {"ms": round(grads["fp32"][0], 3),
                                          "max_abs_diff_vs_fp64": float(np.abs(grads["fp32"][1] - gn).max())}}
-    if args.config == 1 and not args.no_dense:
+    if (args.config in (0, 1) or args.dense) and not args.no_dense:
         plan = Plan.from_problem(p, prec=forms[0], t_b=0.0, t_d=0.0, shell_order=so, grid_block=args.grid_block)
         info = plan.info()
         ms, stage, st, E, V, rho = time_path(plan, D, max(3, args.steps // 2), 1, torch)
